@@ -1,0 +1,75 @@
+"""Exact LP solutions of tiny POT instances (test helper, independent of the oracle).
+
+Two formulations from the paper's appendix "Reformulating POT as Extended OT":
+  * the slack LP: x = (vec X, p, q) >= 0 with X 1 + p = r, X^T 1 + q = c,
+    1^T X 1 = s, minimising <C, X>;
+  * the extended OT LP on the (n+1) x (m+1) instance with the dummy row and
+    column (cost 0) and corner cost A > max C, marginals (r, |c|_1 - s) and
+    (c, |r|_1 - s); its optimum equals the POT optimum.
+Both are solved with scipy's HiGHS.
+"""
+import itertools
+
+import numpy as np
+from scipy.optimize import linprog
+
+
+def pot_lp(C, r, c, s):
+    C = np.asarray(C, dtype=np.float64)
+    n, m = C.shape
+    nv = n * m + n + m
+    A = np.zeros((n + m + 1, nv))
+    for i in range(n):
+        A[i, i * m:(i + 1) * m] = 1.0
+        A[i, n * m + i] = 1.0
+    for j in range(m):
+        A[n + j, j:n * m:m] = 1.0
+        A[n + j, n * m + n + j] = 1.0
+    A[n + m, :n * m] = 1.0
+    b = np.concatenate([r, c, [s]])
+    d = np.concatenate([C.ravel(), np.zeros(n + m)])
+    res = linprog(d, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
+    assert res.status == 0, res.message
+    return float(res.fun), res.x[:n * m].reshape(n, m)
+
+
+def extended_ot_lp(C, r, c, s, A_corner=None):
+    C = np.asarray(C, dtype=np.float64)
+    n, m = C.shape
+    if A_corner is None:
+        A_corner = 2.0 * max(C.max(), 1e-3) + 1.0
+    Ce = np.zeros((n + 1, m + 1))
+    Ce[:n, :m] = C
+    Ce[n, m] = A_corner
+    re = np.concatenate([r, [c.sum() - s]])
+    ce = np.concatenate([c, [r.sum() - s]])
+    N, M = n + 1, m + 1
+    Aeq = np.zeros((N + M, N * M))
+    for i in range(N):
+        Aeq[i, i * M:(i + 1) * M] = 1.0
+    for j in range(M):
+        Aeq[N + j, j::M] = 1.0
+    res = linprog(Ce.ravel(), A_eq=Aeq, b_eq=np.concatenate([re, ce]), bounds=(0, None),
+                  method="highs")
+    assert res.status == 0, res.message
+    return float(res.fun)
+
+
+def assignment_brute_force(C):
+    """Balanced OT with uniform masses 1/n on an n x n cost: by Birkhoff's
+    theorem the optimum is attained at a permutation matrix / n."""
+    C = np.asarray(C)
+    n = C.shape[0]
+    best = min(sum(C[i, p[i]] for i in range(n)) for p in itertools.permutations(range(n)))
+    return best / n
+
+
+def in_polytope(X, r, c, s, rtol=1e-12):
+    X = np.asarray(X)
+    scale = max(1.0, float(np.max(r)), float(np.max(c)), s)
+    tol = rtol * scale
+    ok_nonneg = bool(np.all(X >= -tol))
+    ok_rows = bool(np.all(X.sum(1) <= r + tol))
+    ok_cols = bool(np.all(X.sum(0) <= c + tol))
+    ok_mass = abs(X.sum() - s) <= rtol * max(1.0, s) * 10
+    return ok_nonneg and ok_rows and ok_cols and ok_mass
