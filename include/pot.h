@@ -1,0 +1,187 @@
+/*
+ * pot.h -- C ABI of libpot.so, an MI355X (gfx950) solver for entropic partial
+ * optimal transport (POT) with ASPOT and feasible Sinkhorn.
+ *
+ * Problem (Section 2.1 of Truong et al., "Accelerated Sinkhorn Algorithms for
+ * Partial Optimal Transport"): given a cost C >= 0 (n x m), marginals r >= 0
+ * (n), c >= 0 (m) and a mass 0 < s <= min(|r|_1, |c|_1), find a plan
+ * X in U(r, c, s) = { X >= 0 : X 1 <= r, X^T 1 <= c, 1^T X 1 = s } whose cost
+ * <C, X> is within eps of the optimum (Definition 1).
+ *
+ * Solvers:
+ *   POT_ASPOT    -- Algorithm 2 (setup "Approximating POT", Nesterov coupling,
+ *                   the Greenkhorn step of Algorithm 1, the argmin safeguard,
+ *                   stopping on the error E(t) of Section 3.1);
+ *   POT_SINKHORN -- feasible Sinkhorn: the loop of Algorithm 3 with the
+ *                   default gamma and stopping rule of Algorithm 2, on the
+ *                   extended (n+1) x (m+1) instance of the appendix
+ *                   "Reduction to Extended OT".
+ * Both end with "Form primal" and a rounding onto U(r, c, s) computed in FP64
+ * with the original r, c, s:
+ *   alpha_i = min(1, r_i / (X~ 1)_i);  beta_j = min(1, c_j / (diag(alpha) X~)^T 1)_j;
+ *   X'' = diag(alpha) X~ diag(beta), T'' = |X''|_1;
+ *   Xbar = kappa X'' + lambda p' q'^T with kappa = min(1, s/T''),
+ *   lambda = max(0, s - T'') / (|p'|_1 |q'|_1), p' = r - X'' 1, q' = c - X''^T 1.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked (device) are HIP device pointers on the current device;
+ *     (host) pointers are host memory.  The caller owns every buffer; the
+ *     library keeps no pointer after a call returns and never allocates or
+ *     frees device memory inside a solve: all scratch lives in the caller's
+ *     workspace (size from pot_workspace_bytes*).
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
+ *     pot_solve synchronises the stream before returning, after which the
+ *     host pot_result is filled and all device outputs are written.
+ *   - Dense costs are row-major with leading dimension ldc >= m (elements).
+ *   - Arguments are checked before any work is enqueued that writes outside
+ *     the workspace.  On POT_ERR_INVALID_ARG no output is written.
+ *     pot_last_error() returns a thread-local message for the last failure.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef POT_H
+#define POT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    POT_OK = 0,
+    POT_ERR_INVALID_ARG = 1,     /* bad sizes, masses, eps, pointers or options */
+    POT_ERR_NO_CONVERGENCE = 2,  /* max_iter reached; the rounded plan is still in U(r,c,s) */
+    POT_ERR_NUMERIC = 3,         /* a non-finite statistic (overflow of an FP32 sum) */
+    POT_ERR_DEVICE = 4,          /* a HIP runtime call failed */
+    POT_ERR_WORKSPACE = 5,       /* workspace too small or misaligned (needs 256 B alignment) */
+    POT_ERR_UNSUPPORTED = 6      /* option combination not implemented */
+} pot_status;
+
+typedef enum { POT_ASPOT = 0, POT_SINKHORN = 1 } pot_algo;
+
+typedef enum {
+    POT_COST_F32 = 0,             /* C: float,    n x m, ld = ldc (16-byte aligned rows give vector loads) */
+    POT_COST_BF16 = 1,            /* C: uint16 bfloat16 bit patterns, n x m, ld = ldc */
+    POT_COST_SQEUCLID_POINTS = 3  /* C_ij = cost_scale * |x_i - y_j|^2 from float points, d in {2, 3} */
+} pot_cost_kind;
+
+typedef struct {
+    int32_t n, m;          /* >= 1 */
+    int32_t d;             /* point dimension (points kind only): 2 or 3 */
+    int32_t kind;          /* pot_cost_kind */
+    const void* C;         /* (device) dense cost, or NULL for the points kind */
+    int64_t ldc;           /* leading dimension of C in elements (>= m) */
+    const float* x;        /* (device) n x d row-major source points (points kind) */
+    const float* y;        /* (device) m x d row-major target points (points kind) */
+    double cost_scale;     /* points kind: scale of |x - y|^2; <= 0 means 1 / max_ij |x_i - y_j|^2 */
+    double cmax;           /* max_ij C_ij (enters eps~ = eps / (8 cmax)); <= 0 means computed
+                              on the device (points kind with computed scale: 1) */
+    const double* r;       /* (device) n source masses, finite, >= 0 */
+    const double* c;       /* (device) m target masses, finite, >= 0 */
+    double s;              /* transported mass, 0 < s <= min(|r|_1, |c|_1) */
+} pot_problem;
+
+/* flags */
+#define POT_FLAG_WANT_PLAN 1u      /* write the dense FP64 plan to outputs->plan */
+#define POT_FLAG_NO_ROUND 2u       /* skip the rounding passes (duals only) */
+
+typedef struct {
+    int32_t algo;          /* pot_algo */
+    int32_t max_iter;      /* iteration cap (<= 0: 100000) */
+    double eps;            /* accuracy target of Definition 1 (> 0) */
+    double gamma;          /* entropic parameter; <= 0: eps / (4 ln max(n, m)) (Algorithm 2 setup) */
+    double tol;            /* stopping threshold on E; <= 0: eps~ of Algorithm 2 setup */
+    double A;              /* Sinkhorn corner cost of the extended cost; <= 0: 8 cmax / eps (Algorithm 3) */
+    int32_t block_rule;    /* ASPOT block choice: 0 greedy by decrease score, 1 cyclic u, v, w */
+    int32_t step_rule;     /* ASPOT step: 0 as printed (base zbar, gamma/(3 M theta)),
+                              1 mirror form (base ztilde, 1/(3 M theta)) */
+    int32_t check_every;   /* host polls convergence every k iterations (<= 0: 16) */
+    uint32_t flags;        /* POT_FLAG_* */
+    const double* u0;      /* (device) warm start u (n) in log-scaling units, or NULL (zero start) */
+    const double* v0;      /* (device) warm start v (m), or NULL */
+    double w0;             /* warm start w */
+    const int32_t* force;  /* (device) replay of decisions for tests: 3 ints per ASPOT iteration
+                              {block of z-hat, pick (1 = z-hat), block of z-check or -1 = stop};
+                              NULL = the solver decides */
+    int32_t force_len;     /* iterations covered by force */
+    int32_t* trace_i;      /* (device) per-iteration decisions, 3 ints each, or NULL */
+    double* trace_d;       /* (device) per-iteration values {E, phi(z-check^t), phi(z-hat^t), theta_t}, or NULL */
+    int32_t trace_cap;     /* iterations the trace buffers hold */
+    int32_t tile_rows;     /* rows per tile of the statistics pass (0: autotuned) */
+} pot_options;
+
+typedef struct {
+    int32_t status;        /* pot_status of this solve */
+    int32_t iters;         /* iterations run */
+    int32_t algo;
+    int32_t used_warm;     /* 1 if the warm start was kept */
+    double cost;           /* <C, Xbar> in FP64 */
+    double E;              /* stopping error at the output point */
+    double gamma, tol;
+    double phi;            /* ASPOT: phi at the last z-check */
+    double mass;           /* 1^T Xbar 1 */
+    double kappa, lambda, T2;   /* rounding factors (see the header comment) */
+    double cost_scale, cmax;
+} pot_result;
+
+typedef struct {
+    double* plan;          /* (device) n x m FP64 row-major, written with POT_FLAG_WANT_PLAN, or NULL */
+    double* f;             /* (device) n: X~_ij = exp(f_i + g_j - C_ij / gamma), or NULL */
+    double* g;             /* (device) m, or NULL */
+    double* u;             /* (device) n: ASPOT u at the output point (Sinkhorn: a_1..a_n), or NULL */
+    double* v;             /* (device) m: ASPOT v (Sinkhorn: b_1..b_m), or NULL */
+    double* alpha;         /* (device) n rounding row factors, or NULL */
+    double* beta;          /* (device) m rounding column factors, or NULL */
+    double* pp;            /* (device) n: p' = r - X'' 1, or NULL */
+    double* qq;            /* (device) m: q' = c - X''^T 1, or NULL */
+    double* w;             /* (host) ASPOT w at the output point, or NULL */
+} pot_outputs;
+
+/* Bytes of workspace pot_solve needs for this problem and options (0 on
+ * invalid sizes).  The workspace must be 256-byte aligned device memory. */
+size_t pot_workspace_bytes(const pot_problem* prob, const pot_options* opts);
+
+/* Solve one POT instance.  res (host) receives the result; out (host struct
+ * of device pointers, may be NULL) receives the optional outputs.
+ * Returns res->status (or an argument/device/workspace error). */
+pot_status pot_solve(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
+                     pot_result* res, const pot_outputs* out, void* stream);
+
+/* Workspace for pot_solve_batched over these problems. */
+size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, const pot_options* opts);
+
+/* Solve `batch` independent instances (dense F32/BF16 or points costs, up to
+ * 4096 points per side) in one persistent launch: one workgroup per instance
+ * at a time, instances taken from a device queue largest first.  probs (host
+ * array) describe each instance with device pointers; opts apply to all;
+ * res (host array of batch) receives per-instance results; f_out/g_out
+ * (host arrays of device pointers, may be NULL) receive the log scalings.
+ * Returns POT_OK if every instance is OK, else the first failing status. */
+pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_options* opts,
+                             void* ws, size_t ws_bytes, pot_result* res,
+                             double* const* f_out, double* const* g_out, void* stream);
+
+/* Measurement hook: set up the problem (as pot_solve does) and launch the
+ * fused statistics pass (row sums, column sums and total of B at the start
+ * point u0, v0, w0 of opts, the pass every ASPOT and Sinkhorn iteration runs)
+ * `reps` times on `stream`, each launch bracketed by HIP events recorded
+ * around the dispatch; *avg_ms (host) receives the mean kernel time.
+ * Requires prob->cmax > 0 (and cost_scale > 0 for points).  Writes only the
+ * workspace.  Synchronises the stream. */
+pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
+                         int32_t reps, double* avg_ms, void* stream);
+
+/* Static description of a status code. */
+const char* pot_status_string(pot_status st);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* pot_last_error(void);
+
+/* Library version string. */
+const char* pot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,106 @@
+// pot_internal.h -- shared device/host definitions of libpot (gfx950).
+//
+// Layout of one solve's workspace, the control block the device-side
+// decision logic keeps, and the argument block of the statistics pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pot.h"
+
+namespace pot {
+
+constexpr int kThreads = 256;         // workgroup size of the tiled passes (4 wave64s)
+constexpr int kScal = 8;              // FP64 per-strip partial sums carried to the decider
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.6931471805599453094;
+
+// Passes of the solver.  One launch of the statistics kernel is one pass.
+enum Phase : int {
+    PH_INIT = 0,     // phi at the start point
+    PH_BAR = 1,      // ASPOT: statistics at zbar^t -> gradient
+    PH_GRAVE = 2,    // ASPOT: statistics at z-grave^t -> Greenkhorn step -> z-hat^t, argmin
+    PH_Z = 3,        // ASPOT: statistics at z^t -> E(z^t), stop, Greenkhorn step -> z-check^{t+1}
+    PH_SK_ROW = 4,   // Sinkhorn: row sums at (a^k, b^k) -> error of iterate k, a^{k+1}
+    PH_SK_COL = 5,   // Sinkhorn: column sums at (a^{k+1}, b^k) -> b^{k+1}
+    PH_R1 = 6,       // rounding: FP64 row sums of X~ -> alpha
+    PH_R2 = 7,       // rounding: FP64 column sums of diag(alpha) X~ -> beta, q'
+    PH_R3 = 8,       // rounding: FP64 row sums of X'' and C X'', C q' -> p', cost
+    PH_R4 = 9,       // rounding: dense plan
+};
+
+// Device control block: every scalar of the algorithm lives here, written
+// only by the deciding workgroup of a pass (or the setup kernel) and read by
+// the next pass.
+struct Ctl {
+    // setup (Algorithm 2, "Approximating POT")
+    double gamma, tol, M, eps, s, cmax, cost_scale;
+    double G;              // log2(e) * cost_scale / gamma: exponent slope per unit of stored cost
+    double sum_r, sum_c, sum_rt, sum_ct, log_s, A;
+    double rhat_d, chat_d, lrhat_d, lchat_d;   // Sinkhorn dummy masses and their logs
+    // ASPOT scalar state
+    double theta;
+    double wchk[2], wtil[2], wbar, wgrave, wz;
+    double phichk, phihat, E, T;
+    // Sinkhorn scalar state: a_{n+1} by parity, b_{m+1}, LSE of a_1..a_n and b_1..b_m
+    double ad[2], bd, lse_a, lse_b;
+    // rounding
+    double T2, nq, np, cost1, pcq, kappa, lambda, cost, mass;
+    int32_t t, done, status, bhat, pick, bchk, iters, nonfinite;
+    int32_t out_par;       // Sinkhorn: parity slot of the output a
+    int32_t cyc;           // cyclic block counter
+    int32_t valid;         // setup status (0 ok)
+    int32_t pad_;
+};
+
+// Pointers into one solve's workspace.
+struct Ws {
+    Ctl* ctl;
+    int32_t* rowcnt;       // [ny]  arrivals per row strip
+    int32_t* colcnt;       // [nx]  arrivals per column strip
+    int32_t* glob;         // [4]   arrivals of strip finalisers
+    void* rowpart;         // [nx * n] FP64 row partial sums ([3 * nx * n] in rounding passes)
+    void* colpart;         // [ny * m] FP64 column partial sums
+    double* rowscal;       // [ny * kScal]
+    double* colscal;       // [nx * kScal]
+    // per-row FP64 vectors (n)
+    double *rt, *lrt, *uchk0, *uchk1, *util0, *util1, *ubar, *ugrave, *uz, *du, *alpha, *pp;
+    // per-column FP64 vectors (m)
+    double *ct, *lct, *vchk0, *vchk1, *vtil0, *vtil1, *vbar, *vgrave, *vz, *dv, *beta, *qq;
+};
+
+struct PassArgs {
+    const void* C;
+    int64_t ldc;
+    const float* x;
+    const float* y;
+    const double* r;       // original masses (rounding)
+    const double* c;
+    int32_t n, m, d, kind;
+    int32_t br, bc;        // tile rows, tile columns
+    int32_t nx, ny;        // column strips, row strips
+    int32_t phase;
+    int32_t max_iter, block_rule, step_rule;
+    const double* u0;
+    const double* v0;
+    double w0;
+    const int32_t* force;
+    int32_t force_len;
+    int32_t* trace_i;
+    double* trace_d;
+    int32_t trace_cap;
+    double* plan;          // PH_R4 output
+    Ws ws;
+};
+
+// Arguments of the setup kernel.
+struct SetupArgs {
+    int32_t n, m, algo, nx, ny;
+    double s, eps, gamma_user, tol_user, A_user, cmax, cost_scale, w0;
+    const double* r;
+    const double* c;
+    Ws ws;
+};
+
+}  // namespace pot

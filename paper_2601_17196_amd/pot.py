@@ -1,0 +1,330 @@
+"""Python binding of libpot.so (argument marshalling only).
+
+Every step of a solve runs in the HIP library; this module only builds the
+C structs of include/pot.h from torch tensors (which provide device memory
+and streams) and reads the results back.  It raises if the library is not
+built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import dataclasses
+import os
+
+import numpy as np
+
+__all__ = [
+    "load", "lib_path", "ASPOT", "SINKHORN", "COST_F32", "COST_BF16", "COST_POINTS",
+    "FLAG_WANT_PLAN", "FLAG_NO_ROUND", "Problem", "Options", "Result", "Outputs",
+    "solve", "solve_batched", "workspace_bytes", "status_string", "last_error", "SolveOutput",
+    "PotError", "time_pass",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(HERE, "libpot.so")
+
+ASPOT, SINKHORN = 0, 1
+COST_F32, COST_BF16, COST_POINTS = 0, 1, 3
+FLAG_WANT_PLAN, FLAG_NO_ROUND = 1, 2
+
+OK, ERR_INVALID_ARG, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_WORKSPACE, ERR_UNSUPPORTED = range(7)
+
+
+class PotError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libpot status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("m", ct.c_int32), ("d", ct.c_int32), ("kind", ct.c_int32),
+                ("C", ct.c_void_p), ("ldc", ct.c_int64), ("x", ct.c_void_p), ("y", ct.c_void_p),
+                ("cost_scale", ct.c_double), ("cmax", ct.c_double), ("r", ct.c_void_p),
+                ("c", ct.c_void_p), ("s", ct.c_double)]
+
+
+class Options(ct.Structure):
+    _fields_ = [("algo", ct.c_int32), ("max_iter", ct.c_int32), ("eps", ct.c_double),
+                ("gamma", ct.c_double), ("tol", ct.c_double), ("A", ct.c_double),
+                ("block_rule", ct.c_int32), ("step_rule", ct.c_int32), ("check_every", ct.c_int32),
+                ("flags", ct.c_uint32), ("u0", ct.c_void_p), ("v0", ct.c_void_p), ("w0", ct.c_double),
+                ("force", ct.c_void_p), ("force_len", ct.c_int32), ("trace_i", ct.c_void_p),
+                ("trace_d", ct.c_void_p), ("trace_cap", ct.c_int32), ("tile_rows", ct.c_int32)]
+
+
+class Result(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("iters", ct.c_int32), ("algo", ct.c_int32),
+                ("used_warm", ct.c_int32), ("cost", ct.c_double), ("E", ct.c_double),
+                ("gamma", ct.c_double), ("tol", ct.c_double), ("phi", ct.c_double),
+                ("mass", ct.c_double), ("kappa", ct.c_double), ("lambda_", ct.c_double),
+                ("T2", ct.c_double), ("cost_scale", ct.c_double), ("cmax", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Outputs(ct.Structure):
+    _fields_ = [("plan", ct.c_void_p), ("f", ct.c_void_p), ("g", ct.c_void_p), ("u", ct.c_void_p),
+                ("v", ct.c_void_p), ("alpha", ct.c_void_p), ("beta", ct.c_void_p),
+                ("pp", ct.c_void_p), ("qq", ct.c_void_p), ("w", ct.POINTER(ct.c_double))]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def load():
+    """Load libpot.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = os.environ.get("POT_LIB") or _LIB   # POT_LIB: another build of the same sources
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ct.CDLL(path)
+    lib.pot_workspace_bytes.argtypes = [ct.POINTER(Problem), ct.POINTER(Options)]
+    lib.pot_workspace_bytes.restype = ct.c_size_t
+    lib.pot_workspace_bytes_batched.argtypes = [ct.c_int32, ct.POINTER(Problem), ct.POINTER(Options)]
+    lib.pot_workspace_bytes_batched.restype = ct.c_size_t
+    lib.pot_solve.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
+                              ct.POINTER(Result), ct.POINTER(Outputs), ct.c_void_p]
+    lib.pot_solve.restype = ct.c_int
+    lib.pot_solve_batched.argtypes = [ct.c_int32, ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p,
+                                      ct.c_size_t, ct.POINTER(Result), ct.POINTER(ct.c_void_p),
+                                      ct.POINTER(ct.c_void_p), ct.c_void_p]
+    lib.pot_solve_batched.restype = ct.c_int
+    lib.pot_time_pass.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
+                                  ct.c_int32, ct.POINTER(ct.c_double), ct.c_void_p]
+    lib.pot_time_pass.restype = ct.c_int
+    lib.pot_status_string.argtypes = [ct.c_int]
+    lib.pot_status_string.restype = ct.c_char_p
+    lib.pot_last_error.argtypes = []
+    lib.pot_last_error.restype = ct.c_char_p
+    lib.pot_version.argtypes = []
+    lib.pot_version.restype = ct.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(st: int) -> str:
+    return load().pot_status_string(int(st)).decode()
+
+
+def last_error() -> str:
+    return load().pot_last_error().decode()
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+def make_problem(r, c, s, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=0.0, cmax=0.0):
+    """Build a Problem from device tensors.  C: (n, ldc) float32 or
+    uint16/bfloat16 bit patterns (row-major, the first m columns used);
+    x, y: (n, d), (m, d) float32 points."""
+    import torch
+    n, m = int(r.shape[0]), int(c.shape[0])
+    p = Problem()
+    p.n, p.m = n, m
+    p.r, p.c = _ptr(r), _ptr(c)
+    p.s = float(s)
+    p.cost_scale = float(cost_scale)
+    p.cmax = float(cmax)
+    if C is not None:
+        if kind is None:
+            kind = COST_F32 if C.dtype == torch.float32 else COST_BF16
+        p.kind = kind
+        p.C = _ptr(C)
+        p.ldc = int(ldc if ldc is not None else C.stride(0))
+        p.d = 0
+    else:
+        p.kind = COST_POINTS
+        p.x, p.y = _ptr(x), _ptr(y)
+        p.d = int(x.shape[1])
+    return p
+
+
+def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, block_rule=0,
+                 step_rule=0, check_every=0, flags=0, u0=None, v0=None, w0=0.0, force=None,
+                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0):
+    o = Options()
+    o.algo = int(algo)
+    o.max_iter = int(max_iter)
+    o.eps = float(eps)
+    o.gamma = float(gamma)
+    o.tol = float(tol)
+    o.A = float(A)
+    o.block_rule = int(block_rule)
+    o.step_rule = int(step_rule)
+    o.check_every = int(check_every)
+    o.flags = int(flags)
+    o.u0, o.v0 = _ptr(u0), _ptr(v0)
+    o.w0 = float(w0)
+    o.force = _ptr(force)
+    o.force_len = 0 if force is None else int(force.numel() // 3)
+    o.trace_i, o.trace_d = _ptr(trace_i), _ptr(trace_d)
+    o.trace_cap = int(trace_cap)
+    o.tile_rows = int(tile_rows)
+    return o
+
+
+def workspace_bytes(prob: Problem, opts: Options) -> int:
+    return int(load().pot_workspace_bytes(ct.byref(prob), ct.byref(opts)))
+
+
+@dataclasses.dataclass
+class SolveOutput:
+    status: int
+    result: dict
+    f: object = None
+    g: object = None
+    u: object = None
+    v: object = None
+    w: float = 0.0
+    alpha: object = None
+    beta: object = None
+    pp: object = None
+    qq: object = None
+    plan: object = None
+    trace_i: object = None
+    trace_d: object = None
+
+
+def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=0.0, cmax=0.0,
+          algo=ASPOT, want_plan=False, want_factors=True, workspace=None, stream=None,
+          raise_on_error=True, trace_cap=0, **opt_kw):
+    """Solve one POT instance through pot_solve.  Tensors must be on the GPU."""
+    import torch
+    lib = load()
+    dev = r.device
+    prob = make_problem(r, c, s, C=C, x=x, y=y, kind=kind, ldc=ldc, cost_scale=cost_scale, cmax=cmax)
+    tr_i = tr_d = None
+    if trace_cap > 0:
+        tr_i = torch.full((trace_cap * 3,), -9, dtype=torch.int32, device=dev)
+        tr_d = torch.full((trace_cap * 4,), float("nan"), dtype=torch.float64, device=dev)
+    opts = make_options(eps, algo=algo, flags=(FLAG_WANT_PLAN if want_plan else 0), trace_i=tr_i,
+                        trace_d=tr_d, trace_cap=trace_cap, **opt_kw)
+    nbytes = workspace_bytes(prob, opts)
+    if nbytes == 0:
+        raise PotError(ERR_INVALID_ARG, "invalid sizes")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) & ~255
+    avail = workspace.numel() - (aligned - base)
+    n, m = prob.n, prob.m
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = Outputs()
+    so = SolveOutput(status=-1, result={})
+    so.f, so.g = torch.empty(n, **f64), torch.empty(m, **f64)
+    so.u, so.v = torch.empty(n, **f64), torch.empty(m, **f64)
+    if want_factors:
+        so.alpha, so.pp = torch.empty(n, **f64), torch.empty(n, **f64)
+        so.beta, so.qq = torch.empty(m, **f64), torch.empty(m, **f64)
+    if want_plan:
+        so.plan = torch.empty((n, m), **f64)
+    wbox = ct.c_double(0.0)
+    out.plan = _ptr(so.plan)
+    out.f, out.g, out.u, out.v = _ptr(so.f), _ptr(so.g), _ptr(so.u), _ptr(so.v)
+    out.alpha, out.beta, out.pp, out.qq = _ptr(so.alpha), _ptr(so.beta), _ptr(so.pp), _ptr(so.qq)
+    out.w = ct.pointer(wbox)
+    res = Result()
+    st = lib.pot_solve(ct.byref(prob), ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(avail),
+                       ct.byref(res), ct.byref(out), _stream_ptr(stream))
+    so.status = int(st)
+    so.result = res.as_dict()
+    so.w = wbox.value
+    so.trace_i, so.trace_d = tr_i, tr_d
+    if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
+        raise PotError(st, last_error())
+    return so
+
+
+def solve_batched(problems, eps, algo=ASPOT, stream=None, workspace=None, **opt_kw):
+    """problems: list of dicts with keys r, c, s and C or (x, y) (device tensors).
+    Returns (status, list of result dicts, list of (f, g) tensors)."""
+    import torch
+    lib = load()
+    B = len(problems)
+    probs = (Problem * B)()
+    keep = []
+    for k, pr in enumerate(problems):
+        probs[k] = make_problem(pr["r"], pr["c"], pr["s"], C=pr.get("C"), x=pr.get("x"), y=pr.get("y"),
+                                cost_scale=pr.get("cost_scale", 0.0), cmax=pr.get("cmax", 0.0))
+        keep.append(pr)
+    opts = make_options(eps, algo=algo, **opt_kw)
+    nbytes = int(lib.pot_workspace_bytes_batched(B, probs, ct.byref(opts)))
+    dev = problems[0]["r"].device
+    if workspace is None or workspace.numel() < nbytes + 256:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) & ~255
+    avail = workspace.numel() - (aligned - base)
+    fs = [torch.empty(p["r"].shape[0], dtype=torch.float64, device=dev) for p in problems]
+    gs = [torch.empty(p["c"].shape[0], dtype=torch.float64, device=dev) for p in problems]
+    fp = (ct.c_void_p * B)(*[t.data_ptr() for t in fs])
+    gp = (ct.c_void_p * B)(*[t.data_ptr() for t in gs])
+    res = (Result * B)()
+    st = lib.pot_solve_batched(B, probs, ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(avail), res,
+                               fp, gp, _stream_ptr(stream))
+    return int(st), [res[k].as_dict() for k in range(B)], list(zip(fs, gs))
+
+
+def to_device_instance(inst, device="cuda", kind="f32", pad_ldc=False):
+    """Host Instance (paper_2601_17196_amd.instances) -> dict of device tensors."""
+    import torch
+    from . import instances as I
+    d = {"r": torch.from_numpy(inst.r).to(device), "c": torch.from_numpy(inst.c).to(device), "s": inst.s}
+    if kind == "points":
+        d["x"] = torch.from_numpy(inst.x).to(device)
+        d["y"] = torch.from_numpy(inst.y).to(device)
+        d["cost_scale"] = inst.cost_scale
+        d["cmax"] = 1.0
+        return d
+    if kind == "f32":
+        host = inst.C32
+    elif kind == "bf16":
+        host = I.to_bf16_bits(inst.C32).view(np.int16)
+    else:
+        raise ValueError(kind)
+    n, m = host.shape
+    if pad_ldc:
+        ld = (m + 3) // 4 * 4 + 4
+        buf = np.zeros((n, ld), dtype=host.dtype)
+        buf[:, :m] = host
+        host = buf
+    t = torch.from_numpy(np.ascontiguousarray(host)).to(device)
+    d["C"] = t[:, :m] if pad_ldc else t
+    d["ldc"] = t.stride(0)
+    d["kind"] = COST_F32 if kind == "f32" else COST_BF16
+    d["cmax"] = 0.0
+    return d
+
+
+def time_pass(r, c, s, eps, reps=50, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=0.0,
+              cmax=1.0, u0=None, v0=None, w0=0.0, stream=None, tile_rows=0):
+    """Mean kernel time (ms) of the fused statistics pass at (u0, v0, w0),
+    from HIP events recorded around each dispatch (pot_time_pass)."""
+    import torch
+    lib = load()
+    prob = make_problem(r, c, s, C=C, x=x, y=y, kind=kind, ldc=ldc, cost_scale=cost_scale, cmax=cmax)
+    opts = make_options(eps, u0=u0, v0=v0, w0=w0, tile_rows=tile_rows)
+    nbytes = workspace_bytes(prob, opts)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=r.device)
+    aligned = (ws.data_ptr() + 255) & ~255
+    ms = ct.c_double(0.0)
+    st = lib.pot_time_pass(ct.byref(prob), ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(nbytes),
+                           int(reps), ct.byref(ms), _stream_ptr(stream))
+    if st != OK:
+        raise PotError(st, last_error())
+    return ms.value

@@ -1,0 +1,223 @@
+"""Edge cases and failure handling of the HIP path, through the C ABI."""
+import ctypes as ct
+
+import numpy as np
+import pytest
+
+from oracle import potref as O
+from paper_2601_17196_amd import instances as I
+from tests.gpu_common import feasible, gpu_solve, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _solve_dense(C, r, c, s, eps=1e-2, **kw):
+    import torch
+
+    from paper_2601_17196_amd import pot
+    out = pot.solve(_dev(r), _dev(c), s, eps, C=_dev(C.astype(np.float32)), raise_on_error=False,
+                    want_plan=True, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_single_point():
+    out = _solve_dense(np.array([[0.37]]), np.array([0.9]), np.array([1.4]), 0.6, gamma=1e-2, cmax=1.0)
+    assert out.status == 0
+    X = out.plan.cpu().numpy()
+    assert X[0, 0] == pytest.approx(0.6, rel=1e-14)
+    assert out.result["cost"] == pytest.approx(float(np.float32(0.37)) * 0.6, rel=1e-14)
+
+
+@pytest.mark.parametrize("n,m", [(1, 9), (9, 1), (2, 700), (700, 3)])
+def test_degenerate_shapes(n, m):
+    inst = I.uniform_pair(n, m, 2, 40 + n + m, mass_r=1.0, mass_c=1.0, s_frac=0.5)
+    ref = O.solve(inst.C32.astype(np.float64), inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0)
+    out = gpu_solve(inst, "f32", "aspot", want_plan=True)
+    assert out.status == 0
+    assert out.result["iters"] == ref.iters
+    assert rel(out.result["cost"], ref.rounded["cost"]) <= 1e-6
+    assert feasible(out.plan.cpu().numpy(), inst.r, inst.c, inst.s)
+
+
+def test_constant_cost():
+    n, m, kap = 33, 65, 0.42
+    rng = np.random.default_rng(3)
+    r = rng.dirichlet(np.ones(n)) * 0.9
+    c = rng.dirichlet(np.ones(m)) * 1.1
+    C = np.full((n, m), kap, dtype=np.float32)
+    for algo in (0, 1):
+        out = _solve_dense(C, r, c, 0.5, algo=algo, cmax=float(np.float32(kap)))
+        assert out.status == 0
+        assert out.result["cost"] == pytest.approx(float(np.float32(kap)) * 0.5, rel=1e-12)
+
+
+def test_max_iter_returns_feasible_plan():
+    inst = I.c1(0)
+    out = gpu_solve(inst, "f32", "aspot", max_iter=5, want_plan=True)
+    assert out.status == 2                       # POT_ERR_NO_CONVERGENCE
+    assert out.result["iters"] == 5
+    assert feasible(out.plan.cpu().numpy(), inst.r, inst.c, inst.s)
+    ref = O.solve(inst.C32.astype(np.float64), inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0,
+                  max_iter=5)
+    assert ref.status == 2
+    assert rel(out.result["cost"], ref.rounded["cost"]) <= 1e-6
+    o2 = gpu_solve(inst, "f32", "sinkhorn", max_iter=3, want_plan=True)
+    assert o2.status == 2 and o2.result["iters"] == 3
+    assert feasible(o2.plan.cpu().numpy(), inst.r, inst.c, inst.s)
+
+
+def test_tiny_mass_and_full_mass():
+    inst = I.uniform_pair(120, 90, 2, 50, mass_r=1.0, mass_c=1.0, s_frac=1e-3)
+    ref = O.solve(inst.C32.astype(np.float64), inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0)
+    out = gpu_solve(inst, "f32", "aspot", want_plan=True)
+    assert out.status == 0 and feasible(out.plan.cpu().numpy(), inst.r, inst.c, inst.s)
+    assert rel(out.result["cost"], ref.rounded["cost"]) <= 1e-6
+    inst2 = I.uniform_pair(120, 90, 2, 51, mass_r=1.0, mass_c=1.0, s_frac=1.0)
+    out2 = gpu_solve(inst2, "f32", "sinkhorn", want_plan=True)
+    assert out2.status == 0 and feasible(out2.plan.cpu().numpy(), inst2.r, inst2.c, inst2.s)
+
+
+def test_zero_masses_allowed():
+    inst = I.uniform_pair(50, 40, 2, 52)
+    inst.r[::3] = 0.0
+    inst.s = 0.5 * min(inst.r.sum(), inst.c.sum())
+    ref = O.solve(inst.C32.astype(np.float64), inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0)
+    out = gpu_solve(inst, "f32", "aspot", want_plan=True)
+    X = out.plan.cpu().numpy()
+    assert feasible(X, inst.r, inst.c, inst.s)
+    assert np.all(X[::3] == 0.0)
+    assert rel(out.result["cost"], ref.rounded["cost"]) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# failure handling: documented statuses, nothing written on argument errors
+# ---------------------------------------------------------------------------
+def test_invalid_mass_rejected():
+    from paper_2601_17196_amd import pot
+    inst = I.uniform_pair(30, 20, 2, 60)
+    C = inst.C32
+    out = _solve_dense(C, inst.r, inst.c, 1.5 * inst.r.sum())
+    assert out.status == pot.ERR_INVALID_ARG
+    r = inst.r.copy()
+    r[3] = -1e-3
+    out = _solve_dense(C, r, inst.c, 0.1)
+    assert out.status == pot.ERR_INVALID_ARG
+    r[3] = np.nan
+    out = _solve_dense(C, r, inst.c, 0.1)
+    assert out.status == pot.ERR_INVALID_ARG
+    assert "non-finite" in pot.last_error() or "negative" in pot.last_error()
+
+
+def test_bad_cost_rejected_when_scanned():
+    from paper_2601_17196_amd import pot
+    inst = I.uniform_pair(30, 20, 2, 61)
+    C = inst.C32.copy()
+    C[4, 5] = np.nan
+    out = _solve_dense(C, inst.r, inst.c, inst.s, cmax=0.0)
+    assert out.status == pot.ERR_INVALID_ARG
+    C[4, 5] = -0.5
+    out = _solve_dense(C, inst.r, inst.c, inst.s, cmax=0.0)
+    assert out.status == pot.ERR_INVALID_ARG
+
+
+def test_bad_options_rejected():
+    from paper_2601_17196_amd import pot
+    inst = I.uniform_pair(30, 20, 2, 62)
+    out = _solve_dense(inst.C32, inst.r, inst.c, inst.s, eps=-1.0)
+    assert out.status == pot.ERR_INVALID_ARG
+    out = _solve_dense(inst.C32, inst.r, inst.c, inst.s, block_rule=7)
+    assert out.status == pot.ERR_INVALID_ARG
+    out = _solve_dense(inst.C32, inst.r, inst.c, inst.s, tile_rows=1000)
+    assert out.status == pot.ERR_INVALID_ARG
+
+
+def test_workspace_too_small():
+    import torch
+
+    from paper_2601_17196_amd import pot
+    lib = pot.load()
+    inst = I.uniform_pair(30, 20, 2, 63)
+    d = pot.to_device_instance(inst, "cuda:0")
+    prob = pot.make_problem(d["r"], d["c"], d["s"], C=d["C"], cmax=1.0)
+    opts = pot.make_options(1e-2)
+    need = pot.workspace_bytes(prob, opts)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    res = pot.Result()
+    st = lib.pot_solve(ct.byref(prob), ct.byref(opts), ct.c_void_p(ws.data_ptr()), ct.c_size_t(need - 256),
+                       ct.byref(res), None, None)
+    assert st == pot.ERR_WORKSPACE
+    st = lib.pot_solve(ct.byref(prob), ct.byref(opts), ct.c_void_p(ws.data_ptr() + 8), ct.c_size_t(need),
+                       ct.byref(res), None, None)
+    assert st == pot.ERR_WORKSPACE
+    prob.ldc = 5
+    st = lib.pot_solve(ct.byref(prob), ct.byref(opts), ct.c_void_p(ws.data_ptr()), ct.c_size_t(need),
+                       ct.byref(res), None, None)
+    assert st == pot.ERR_INVALID_ARG
+
+
+def test_warm_start_at_optimum_converges_immediately():
+    """Starting from the oracle's converged duals, one iteration suffices and
+    the cost matches."""
+    import torch
+    inst = I.c1(0)
+    C = inst.C32.astype(np.float64)
+    gam, tol, M, rt, ct_ = O.setup(inst.r, inst.c, inst.s, inst.eps, cmax=1.0)
+    u, v, w, it, E, st, _ = O.aspot(C, gam, 1e-9, rt, ct_, inst.s, M)
+    ref = O.solve(C, inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0, z0=(u, v, w))
+    out = gpu_solve(inst, "f32", "aspot", u0=torch.from_numpy(u).cuda(), v0=torch.from_numpy(v).cuda(),
+                    w0=w)
+    assert out.status == 0 and out.result["used_warm"] == 1
+    assert out.result["iters"] == ref.iters <= 2
+    assert rel(out.result["cost"], ref.rounded["cost"]) <= 1e-6
+
+
+@pytest.mark.parametrize("algo", ["aspot", "sinkhorn"])
+def test_far_apart_points_underflow_at_start(algo):
+    """min C/gamma ~ 135: every term of B(0) is below the FP32 range; the
+    tiles re-sweep with a shift and the solve matches the oracle."""
+    inst = I.uniform_pair(1, 9, 2, 50, mass_r=1.0, mass_c=1.0, s_frac=0.5)
+    ref = O.solve(inst.C32.astype(np.float64), inst.r, inst.c, inst.s, inst.eps, algo=algo, cmax=1.0)
+    out = gpu_solve(inst, "f32", algo, want_plan=True)
+    assert out.status == 0
+    assert feasible(out.plan.cpu().numpy(), inst.r, inst.c, inst.s)
+    assert abs(out.result["cost"] - ref.rounded["cost"]) <= inst.eps
+
+
+def test_unrepresentable_start_reports_numeric():
+    """A start point with B(z0) ~ e^100 makes the first (unguarded) gradient
+    step of ASPOT jump to z ~ -1e39, where B underflows even the FP64 range;
+    the FP64 log-domain oracle carries on, the GPU path reports
+    POT_ERR_NUMERIC instead of returning a wrong plan."""
+    import torch
+
+    from paper_2601_17196_amd import pot
+    inst = I.uniform_pair(90, 70, 2, 53)
+    n, m = inst.C32.shape
+    u0 = np.full(n, 50.0)
+    v0 = np.full(m, 50.0)
+    out = gpu_solve(inst, "f32", "aspot", u0=torch.from_numpy(u0).cuda(), v0=torch.from_numpy(v0).cuda())
+    assert out.status == pot.ERR_NUMERIC
+
+
+def test_moderate_warm_start_matches_oracle():
+    """A warm start off the optimum (B(z0) up to e^3) follows the oracle."""
+    import torch
+    inst = I.uniform_pair(90, 70, 2, 54)
+    C = inst.C32.astype(np.float64)
+    n, m = C.shape
+    rng = np.random.default_rng(5)
+    u0 = rng.normal(0.0, 1.0, n) + 1.0
+    v0 = rng.normal(0.0, 1.0, m) + 1.0
+    ref = O.solve(C, inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0, z0=(u0, v0, 0.5))
+    out = gpu_solve(inst, "f32", "aspot", u0=torch.from_numpy(u0).cuda(), v0=torch.from_numpy(v0).cuda(),
+                    w0=0.5)
+    assert out.status == 0
+    assert abs(out.result["cost"] - ref.rounded["cost"]) <= inst.eps
+    if out.result["iters"] == ref.iters:
+        assert rel(out.result["cost"], ref.rounded["cost"]) <= 1e-6
