@@ -85,6 +85,8 @@ typedef struct {
 /* flags */
 #define POT_FLAG_WANT_PLAN 1u      /* write the dense FP64 plan to outputs->plan */
 #define POT_FLAG_NO_ROUND 2u       /* skip the rounding passes (duals only) */
+#define POT_FLAG_NO_GRAPH 4u       /* launch every kernel from the host instead of replaying a
+                                      captured HIP graph of check_every iterations */
 
 typedef struct {
     int32_t algo;          /* pot_algo */
@@ -162,15 +164,17 @@ pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_
                              void* ws, size_t ws_bytes, pot_result* res,
                              double* const* f_out, double* const* g_out, void* stream);
 
-/* Measurement hook: set up the problem (as pot_solve does) and launch the
- * fused statistics pass (row sums, column sums and total of B at the start
- * point u0, v0, w0 of opts, the pass every ASPOT and Sinkhorn iteration runs)
- * `reps` times on `stream`, each launch bracketed by HIP events recorded
- * around the dispatch; *avg_ms (host) receives the mean kernel time.
- * Requires prob->cmax > 0 (and cost_scale > 0 for points).  Writes only the
- * workspace.  Synchronises the stream. */
+/* Measurement hook: set up the problem (as pot_solve does) and run the
+ * statistics pass (row sums, column sums and total of B at the start point
+ * u0, v0, w0 of opts: the pass every ASPOT and Sinkhorn iteration runs)
+ * `reps` times on `stream`.  A pass is two kernels, the tile kernel that
+ * streams C (or recomputes it from points) and the finalising kernel; each
+ * dispatch is bracketed by HIP events recorded around it.  *avg_ms (host)
+ * receives the mean time of the tile kernel, *fin_ms (host, may be NULL) that
+ * of the finalising kernel.  Requires prob->cmax > 0 (and cost_scale > 0 for
+ * points).  Writes only the workspace.  Synchronises the stream. */
 pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
-                         int32_t reps, double* avg_ms, void* stream);
+                         int32_t reps, double* avg_ms, double* fin_ms, void* stream);
 
 /* Static description of a status code. */
 const char* pot_status_string(pot_status st);

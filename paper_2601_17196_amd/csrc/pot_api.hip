@@ -23,7 +23,8 @@ hipError_t launch_finish(const PassArgs& A, int algo, double* f, double* g, doub
 hipError_t launch_copy_out(const PassArgs& A, double* alpha, double* beta, double* pp, double* qq,
                            hipStream_t st);
 
-hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
+                              hipEvent_t e3);
 
 static thread_local std::string g_last_error;
 
@@ -71,10 +72,11 @@ static size_t layout(const pot_problem* p, const Geometry& g, char* base, Ws* ws
     w.rowcnt = (int32_t*)take(sizeof(int32_t) * (size_t)g.ny);
     w.colcnt = (int32_t*)take(sizeof(int32_t) * (size_t)g.nx);
     w.glob = (int32_t*)take(sizeof(int32_t) * 4);
+    w.tshift = (int32_t*)take(sizeof(int32_t) * (size_t)g.nx * g.ny);
     w.rowpart = take(std::max<size_t>(4 * (size_t)g.nx * n, 8 * 3 * (size_t)g.nx * n));
     w.colpart = take(8 * (size_t)g.ny * m);
-    w.rowscal = (double*)take(8 * (size_t)g.ny * kScal);
-    w.colscal = (double*)take(8 * (size_t)g.nx * kScal);
+    w.rowscal = (double*)take(8 * (size_t)std::max(g.ny, (p->n + 63) / 64) * kScal);
+    w.colscal = (double*)take(8 * (size_t)std::max(g.nx, (p->m + 63) / 64) * kScal);
     double** rv[] = {&w.rt, &w.lrt, &w.uchk0, &w.uchk1, &w.util0, &w.util1,
                      &w.ubar, &w.ugrave, &w.uz, &w.du, &w.alpha, &w.pp};
     for (double** q : rv) *q = (double*)take(8 * (size_t)n);
@@ -144,6 +146,75 @@ static pot_status ensure_poll() {
     return POT_OK;
 }
 
+// The iteration loop as a HIP graph: one chunk of `chunk` iterations (every
+// launch of a phase has the same arguments: the kernels read the iteration
+// state from the control block) is captured once on a private stream and
+// replayed on the caller's stream.  Executables are cached per thread by the
+// bytes of their launch arguments.
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+static thread_local GraphEntry g_graphs[8];
+static thread_local int g_graph_next = 0;
+static thread_local hipStream_t g_capture_stream = nullptr;
+
+static void enqueue_iterations(PassArgs A, int algo, int iters, hipStream_t st, hipError_t* err) {
+    for (int it = 0; it < iters && *err == hipSuccess; ++it) {
+        if (algo == POT_ASPOT) {
+            for (int ph : {PH_BAR, PH_GRAVE, PH_Z}) {
+                A.phase = ph;
+                *err = launch_stats(A, st);
+                if (*err != hipSuccess) return;
+            }
+        } else {
+            A.phase = PH_SK_ROW;
+            *err = launch_stats(A, st);
+            if (*err != hipSuccess) return;
+            A.phase = PH_SK_COL;
+            *err = launch_stats(A, st);
+        }
+    }
+}
+
+static hipError_t chunk_graph(const PassArgs& A, int algo, int chunk, hipGraphExec_t* out) {
+    std::string key((const char*)&A, sizeof(A));
+    key.append((const char*)&algo, sizeof(algo));
+    key.append((const char*)&chunk, sizeof(chunk));
+    for (auto& g : g_graphs)
+        if (g.exec && g.key == key) {
+            *out = g.exec;
+            return hipSuccess;
+        }
+    hipError_t e;
+    if (!g_capture_stream) {
+        e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    enqueue_iterations(A, algo, chunk, g_capture_stream, &le);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g_capture_stream, &graph);
+    if (le != hipSuccess) e = le;
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    GraphEntry& slot = g_graphs[g_graph_next];
+    g_graph_next = (g_graph_next + 1) % 8;
+    if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+    slot.exec = exec;
+    slot.key = key;
+    *out = exec;
+    return hipSuccess;
+}
+
 static pot_status solve_one(const pot_problem* p, const pot_options* o, void* wsp, size_t ws_bytes,
                             pot_result* res, const pot_outputs* out, hipStream_t st) {
     pot_status cs = check_problem(p, o);
@@ -189,6 +260,15 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
         if (!(cmax > 0.0)) return fail(POT_ERR_INVALID_ARG, "cost is identically 0 (|C|_max = 0)");
     }
 
+    // every exponent log2(e) C_ij / gamma must stay below 2^29 (the kernels
+    // split exponents into an int32 part and a fraction)
+    {
+        const int N = std::max(p->n, p->m);
+        const double gam = o->gamma > 0.0 ? o->gamma : o->eps / (4.0 * std::log((double)N));
+        if (!(1.4426950408889634 * cmax / gam < 536870912.0))
+            return fail(POT_ERR_INVALID_ARG, "|C|_max / gamma too large (exponents beyond 2^29)");
+    }
+
     // --- setup (Algorithm 2, "Approximating POT") and validation of r, c, s
     SetupArgs S;
     S.n = p->n; S.m = p->m; S.algo = o->algo; S.nx = g.nx; S.ny = g.ny;
@@ -212,6 +292,7 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     A.C = p->C; A.ldc = p->ldc; A.x = p->x; A.y = p->y; A.r = p->r; A.c = p->c;
     A.n = p->n; A.m = p->m; A.d = p->d; A.kind = p->kind;
     A.br = g.br; A.bc = g.bc; A.nx = g.nx; A.ny = g.ny;
+    A.nrb = (p->n + 63) / 64; A.ncb = (p->m + 63) / 64;
     A.max_iter = o->max_iter > 0 ? o->max_iter : 100000;
     A.block_rule = o->block_rule; A.step_rule = o->step_rule;
     A.u0 = o->u0; A.v0 = o->v0; A.w0 = o->w0;
@@ -228,20 +309,16 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     }
     int enq = 0, k = 0;
     bool done = false;
+    hipGraphExec_t gexec = nullptr;
+    if (!(o->flags & POT_FLAG_NO_GRAPH) && A.max_iter >= chunk) HIPCHK(chunk_graph(A, o->algo, chunk, &gexec));
     while (!done && enq < A.max_iter) {
         const int todo = std::min(chunk, A.max_iter - enq);
-        for (int it = 0; it < todo; ++it) {
-            if (o->algo == POT_ASPOT) {
-                for (int ph : {PH_BAR, PH_GRAVE, PH_Z}) {
-                    A.phase = ph;
-                    HIPCHK(launch_stats(A, st));
-                }
-            } else {
-                A.phase = PH_SK_ROW;
-                HIPCHK(launch_stats(A, st));
-                A.phase = PH_SK_COL;
-                HIPCHK(launch_stats(A, st));
-            }
+        if (gexec && todo == chunk) {
+            HIPCHK(hipGraphLaunch(gexec, st));
+        } else {
+            hipError_t le = hipSuccess;
+            enqueue_iterations(A, o->algo, todo, st, &le);
+            HIPCHK(le);
         }
         enq += todo;
         const int slot = k & 1;
@@ -352,7 +429,7 @@ pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_
 }
 
 pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
-                         int32_t reps, double* avg_ms, void* stream) {
+                         int32_t reps, double* avg_ms, double* fin_ms, void* stream) {
     try {
         if (reps < 1 || !avg_ms) return fail(POT_ERR_INVALID_ARG, "reps >= 1 and avg_ms required");
         pot_status cs = check_problem(prob, opts);
@@ -377,18 +454,22 @@ pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void*
         A.C = prob->C; A.ldc = prob->ldc; A.x = prob->x; A.y = prob->y; A.r = prob->r; A.c = prob->c;
         A.n = prob->n; A.m = prob->m; A.d = prob->d; A.kind = prob->kind;
         A.br = g.br; A.bc = g.bc; A.nx = g.nx; A.ny = g.ny;
+        A.nrb = (prob->n + 63) / 64; A.ncb = (prob->m + 63) / 64;
         A.max_iter = 1; A.u0 = opts->u0; A.v0 = opts->v0; A.w0 = opts->w0;
         A.ws = w;
         A.phase = PH_INIT;
-        std::vector<hipEvent_t> ev(2 * (size_t)reps);
+        std::vector<hipEvent_t> ev(4 * (size_t)reps);
         for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-        for (int k = 0; k < reps; ++k) HIPCHK(launch_stats_timed(A, st, ev[2 * k], ev[2 * k + 1]));
+        for (int k = 0; k < reps; ++k)
+            HIPCHK(launch_stats_timed(A, st, ev[4 * k], ev[4 * k + 1], ev[4 * k + 2], ev[4 * k + 3]));
         HIPCHK(hipStreamSynchronize(st));
-        double tot = 0.0;
+        double tot = 0.0, tot2 = 0.0;
         for (int k = 0; k < reps; ++k) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+            float ms = 0.f, ms2 = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[4 * k], ev[4 * k + 1]));
+            HIPCHK(hipEventElapsedTime(&ms2, ev[4 * k + 2], ev[4 * k + 3]));
             tot += ms;
+            tot2 += ms2;
         }
         for (auto& e : ev) (void)hipEventDestroy(e);
         Ctl hc;
@@ -396,6 +477,7 @@ pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void*
         if (hc.valid != 0) return fail(POT_ERR_INVALID_ARG, "invalid problem");
         if (hc.status != POT_OK) return fail((pot_status)hc.status, "pass reported a non-finite sum");
         *avg_ms = tot / reps;
+        if (fin_ms) *fin_ms = tot2 / reps;
         return POT_OK;
     } catch (...) {
         return fail(POT_ERR_DEVICE, "internal error");

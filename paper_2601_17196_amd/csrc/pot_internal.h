@@ -60,10 +60,11 @@ struct Ws {
     int32_t* rowcnt;       // [ny]  arrivals per row strip
     int32_t* colcnt;       // [nx]  arrivals per column strip
     int32_t* glob;         // [4]   arrivals of strip finalisers
+    int32_t* tshift;       // [nx * ny] per-tile exponent shift, kept across passes
     void* rowpart;         // [nx * n] FP64 row partial sums ([3 * nx * n] in rounding passes)
     void* colpart;         // [ny * m] FP64 column partial sums
-    double* rowscal;       // [ny * kScal]
-    double* colscal;       // [nx * kScal]
+    double* rowscal;       // [nrb * kScal] block sums of the finalising pass (rows)
+    double* colscal;       // [ncb * kScal] (columns); the rounding passes use [ny] / [nx]
     // per-row FP64 vectors (n)
     double *rt, *lrt, *uchk0, *uchk1, *util0, *util1, *ubar, *ugrave, *uz, *du, *alpha, *pp;
     // per-column FP64 vectors (m)
@@ -80,6 +81,7 @@ struct PassArgs {
     int32_t n, m, d, kind;
     int32_t br, bc;        // tile rows, tile columns
     int32_t nx, ny;        // column strips, row strips
+    int32_t nrb, ncb;      // 64-row and 64-column blocks of the finalising pass
     int32_t phase;
     int32_t max_iter, block_rule, step_rule;
     const double* u0;

@@ -1,20 +1,22 @@
 // pot_kernels.hip -- device code of libpot for gfx950 (MI355X).
 //
-// One launch of `stats_pass` is one pass over the cost: every workgroup
+// One pass over the cost is two launches.  In `stats_pass` every workgroup
 // (WG) owns a tile of BR rows x BC columns, forms the exponent
 //     t_ij = log2(e) (u_i + v_j + w - C_ij / gamma)   (in FP64)
 // takes 2^t in FP32 and accumulates FP64 row and column partial sums of the
-// tile (B(z)'s row sums R, column sums Q and total T, Section 2.1).  The last
-// WG to finish a row strip (column strip) reduces that strip's partials in
-// FP64 and applies the per-row (per-column) step of the algorithm; the last
-// strip to finish makes the scalar decisions of the iteration (block choice,
-// argmin, stopping) for the next launch.  No host round trip per iteration.
+// tile (B(z)'s row sums R, column sums Q and total T, Section 2.1).  In
+// `fin_pass` each WG reduces the partials of 64 rows or columns and applies
+// the per-row (per-column) step of the algorithm; the last WG makes the
+// scalar decisions of the iteration (block choice, argmin, stopping) for the
+// next pass.  No host round trip per iteration.
 //
 // The FP64 rounding passes (`round_pass`) use the same tile/strip scheme with
 // an FP64 exponential and FP64 accumulation.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "pot_internal.h"
 
@@ -109,21 +111,19 @@ __device__ __forceinline__ double logaddexp(double a, double b) {
 
 // rho(a, b) = b - a + a log(a / b) (Section 2.1 notation) as a * h(d),
 // d = b/a - 1, h(d) = d - log(1 + d).  For |d| < 1/2 with y = d / (2 + d):
-// log(1 + d) = 2 atanh(y), so h = 2 y^2 / (1 - y) - 2 (y^3/3 + y^5/5 + ...),
-// free of cancellation.  lb = log b, la = log a.
+// log(1 + d) = 2 atanh(y), so h = 2 y^2 / (1 - y) - 2 y^3 sum_k y^{2k} / (2k + 3),
+// free of cancellation; |y| <= 1/3 and 18 terms leave a relative error below
+// 1e-17.  lb = log b, la = log a.
 __device__ double rho_log(double a, double la, double lb) {
-    double d = expm1(lb - la);
+    const double d = expm1(lb - la);
     double h;
     if (fabs(d) < 0.5) {
-        double y = d / (2.0 + d), y2 = y * y;
-        double term = y * y2, ser = 0.0;
-        for (int k = 3; k < 64; k += 2) {
-            double add = term / k;
-            ser += add;
-            if (fabs(add) <= 1e-17 * fabs(ser)) break;
-            term *= y2;
-        }
-        h = 2.0 * y2 / (1.0 - y) - 2.0 * ser;
+        const double y = d / (2.0 + d), y2 = y * y;
+        double p = 1.0 / 39.0;             // k = 18
+#pragma unroll
+        for (int k = 17; k >= 0; --k) p = fma(p, y2, 1.0 / (2 * k + 3));
+        // p = sum_{k=0}^{18} y^{2k} / (2k + 3) (Horner)
+        h = 2.0 * y2 / (1.0 - y) - 2.0 * y * y2 * p;
     } else {
         h = d - log1p(d);
     }
@@ -145,13 +145,11 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
 // t = k + f with k = rint(t) taken from the low word of t + 1.5 * 2^52 (exact
 // for |t| < 2^31) and f = t - k in [-1/2, 1/2] exact in FP64; 2^f in FP32,
 // then scaled by 2^k.  Rounding t itself to FP32 would cost |t| * 2^-24.
-// The low clamp keeps k in range.  k is returned so that the tile can track
-// its largest term's binary exponent.
-__device__ __forceinline__ float exp2_split(double t, int& k) {
+// Callers keep |t| < 2^31 (the duals are clamped, |G C| is bounded).
+__device__ __forceinline__ float exp2_split(double t) {
     const double magic = 6755399441055744.0;   // 1.5 * 2^52
-    t = fmax(t, -4096.0);
     const double mm = t + magic;
-    k = __double2loint(mm);
+    const int k = __double2loint(mm);
     const double f = t - (mm - magic);
     return ldexpf(__builtin_amdgcn_exp2f((float)f), k);
 }
@@ -188,90 +186,83 @@ __device__ __forceinline__ void load_costs(const PassArgs& A, int i, int j, bool
 }
 
 // ---------------------------------------------------------------------------
-// points of the passes: the value of the row / column dual variable at the
-// point a pass evaluates, with the state writes of that phase (done by the
-// strip's "writer" WG only; every WG of the strip computes the same value).
+// points of the passes: the value of a row (u) or column (v) dual variable at
+// the point a pass evaluates, with the state writes of that phase, done by
+// the strip's "writer" workgroup only (every WG of the strip computes the same
+// value).  The candidate state values are loaded first (`load_cand`), before
+// the control block is read, and combined with its scalars afterwards
+// (`eval_point`).  side 0 = rows (u, block u), side 1 = columns (v, block v).
 // ---------------------------------------------------------------------------
-__device__ double row_point(const PassArgs& A, const Ctl& c, int i, bool writer) {
+struct SideVecs {
+    const double* init;
+    double *chk0, *chk1, *til0, *til1, *bar, *grave, *z, *d;
+};
+
+__device__ __forceinline__ SideVecs side_vecs(const PassArgs& A, int side) {
     const Ws& w = A.ws;
-    const int par = c.t & 1;
-    switch (A.phase) {
-    case PH_INIT: {
-        double u0 = A.u0 ? A.u0[i] : 0.0;
-        if (writer) { st_agent(&w.uchk0[i], u0); st_agent(&w.util0[i], u0); }
-        return u0;
-    }
-    case PH_BAR: {
-        double uc;
-        if (c.t == 0) uc = w.uchk0[i];
-        else {
-            // z-check^t = GreenkhornStep(z^{t-1}); du holds the u-block delta at z^{t-1}
-            uc = w.uz[i] + (c.bchk == 0 ? w.du[i] : 0.0);
-            if (writer) st_agent(&(par ? w.uchk1 : w.uchk0)[i], uc);
-        }
-        double ut = (par ? w.util1 : w.util0)[i];
-        double ub = (1.0 - c.theta) * uc + c.theta * ut;
-        if (writer) st_agent(&w.ubar[i], ub);
-        return ub;
-    }
-    case PH_GRAVE: {
-        double ub = w.ubar[i], ut = (par ? w.util1 : w.util0)[i], g = w.du[i];
-        double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
-        double ut1 = (A.step_rule == 0 ? ub : ut) - eta * g;
-        double ug = ub + c.theta * (ut1 - ut);
-        if (writer) { st_agent(&(par ? w.util0 : w.util1)[i], ut1); st_agent(&w.ugrave[i], ug); }
-        return ug;
-    }
-    case PH_Z: {
-        double uh = w.ugrave[i] + (c.bhat == 0 ? w.du[i] : 0.0);
-        double z = c.pick ? uh : (par ? w.uchk1 : w.uchk0)[i];
-        if (writer) st_agent(&w.uz[i], z);
-        return z;
-    }
-    case PH_SK_ROW: return (par ? w.uchk1 : w.uchk0)[i];
-    case PH_SK_COL: return (par ? w.uchk0 : w.uchk1)[i];
-    default: return w.ubar[i];   // rounding passes: f
-    }
+    if (side == 0) return {A.u0, w.uchk0, w.uchk1, w.util0, w.util1, w.ubar, w.ugrave, w.uz, w.du};
+    return {A.v0, w.vchk0, w.vchk1, w.vtil0, w.vtil1, w.vbar, w.vgrave, w.vz, w.dv};
 }
 
-__device__ double col_point(const PassArgs& A, const Ctl& c, int j, bool writer) {
-    const Ws& w = A.ws;
+struct Cand {
+    double q0, q1, q2, q3, q4;
+};
+
+__device__ __forceinline__ Cand load_cand(const PassArgs& A, const SideVecs& V, int side, int i) {
+    Cand q = {0.0, 0.0, 0.0, 0.0, 0.0};
+    switch (A.phase) {
+    case PH_INIT: q.q0 = V.init ? V.init[i] : 0.0; break;
+    case PH_BAR: q.q0 = V.chk0[i]; q.q1 = V.z[i]; q.q2 = V.d[i]; q.q3 = V.til0[i]; q.q4 = V.til1[i]; break;
+    case PH_GRAVE: q.q0 = V.bar[i]; q.q1 = V.til0[i]; q.q2 = V.til1[i]; q.q3 = V.d[i]; break;
+    case PH_Z: q.q0 = V.grave[i]; q.q1 = V.d[i]; q.q2 = V.chk0[i]; q.q3 = V.chk1[i]; break;
+    case PH_SK_ROW:
+    case PH_SK_COL:
+        if (side == 0) { q.q0 = V.chk0[i]; q.q1 = V.chk1[i]; }   // a^k by parity
+        else q.q0 = V.z[i];                                      // b^k
+        break;
+    default: break;
+    }
+    return q;
+}
+
+__device__ double eval_point(const PassArgs& A, const Ctl& c, const SideVecs& V, const Cand& q, int side,
+                             int i, bool writer) {
     const int par = c.t & 1;
     switch (A.phase) {
-    case PH_INIT: {
-        double v0 = A.v0 ? A.v0[j] : 0.0;
-        if (writer) { st_agent(&w.vchk0[j], v0); st_agent(&w.vtil0[j], v0); }
-        return v0;
-    }
+    case PH_INIT:
+        if (writer) { V.chk0[i] = q.q0; V.til0[i] = q.q0; }
+        return q.q0;
     case PH_BAR: {
-        double vc;
-        if (c.t == 0) vc = w.vchk0[j];
-        else {
-            vc = w.vz[j] + (c.bchk == 1 ? w.dv[j] : 0.0);
-            if (writer) st_agent(&(par ? w.vchk1 : w.vchk0)[j], vc);
+        // z-check^t = GreenkhornStep(z^{t-1}): d holds this block's delta at z^{t-1}
+        double xc = q.q0;
+        if (c.t != 0) {
+            xc = q.q1 + (c.bchk == side ? q.q2 : 0.0);
+            if (writer) (par ? V.chk1 : V.chk0)[i] = xc;
         }
-        double vt = (par ? w.vtil1 : w.vtil0)[j];
-        double vb = (1.0 - c.theta) * vc + c.theta * vt;
-        if (writer) st_agent(&w.vbar[j], vb);
-        return vb;
+        const double xt = par ? q.q4 : q.q3;
+        const double xb = (1.0 - c.theta) * xc + c.theta * xt;    // zbar^t
+        if (writer) V.bar[i] = xb;
+        return xb;
     }
     case PH_GRAVE: {
-        double vb = w.vbar[j], vt = (par ? w.vtil1 : w.vtil0)[j], g = w.dv[j];
-        double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
-        double vt1 = (A.step_rule == 0 ? vb : vt) - eta * g;
-        double vg = vb + c.theta * (vt1 - vt);
-        if (writer) { st_agent(&(par ? w.vtil0 : w.vtil1)[j], vt1); st_agent(&w.vgrave[j], vg); }
-        return vg;
+        // z~^{t+1} = base - eta grad phi(zbar); z-grave = zbar + theta (z~^{t+1} - z~^t)
+        const double xb = q.q0, xt = par ? q.q2 : q.q1, g = q.q3;
+        const double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
+        const double xt1 = (A.step_rule == 0 ? xb : xt) - eta * g;
+        const double xg = xb + c.theta * (xt1 - xt);
+        if (writer) { (par ? V.til0 : V.til1)[i] = xt1; V.grave[i] = xg; }
+        return xg;
     }
     case PH_Z: {
-        double vh = w.vgrave[j] + (c.bhat == 1 ? w.dv[j] : 0.0);
-        double z = c.pick ? vh : (par ? w.vchk1 : w.vchk0)[j];
-        if (writer) st_agent(&w.vz[j], z);
+        // z-hat^t = GreenkhornStep(z-grave^t); z^t = argmin phi over {z-check^t, z-hat^t}
+        const double xh = q.q0 + (c.bhat == side ? q.q1 : 0.0);
+        const double z = c.pick ? xh : (par ? q.q3 : q.q2);
+        if (writer) V.z[i] = z;
         return z;
     }
-    case PH_SK_ROW:
-    case PH_SK_COL: return w.vz[j];
-    default: return w.vbar[j];   // rounding passes: g
+    case PH_SK_ROW: return side == 0 ? (par ? q.q1 : q.q0) : q.q0;   // a^k, b^k
+    case PH_SK_COL: return side == 0 ? (par ? q.q0 : q.q1) : q.q0;   // a^{k+1}, b^k
+    default: return 0.0;
     }
 }
 
@@ -296,14 +287,14 @@ __device__ void row_step(const PassArgs& A, const Ctl& c, int i, double R, doubl
     const Ws& w = A.ws;
     switch (A.phase) {
     case PH_INIT: {
-        double u = ld_agent(&w.uchk0[i]);
+        double u = w.uchk0[i];
         acc[0] += R; acc[1] += exp(u); acc[2] += w.rt[i] * u;
         acc[7] += isfinite(R) ? 0.0 : 1.0;
         break;
     }
     case PH_BAR: {
         // gradient of phi at zbar (Section 2.1): R + e^u - r~
-        double u = ld_agent(&w.ubar[i]);
+        double u = w.ubar[i];
         w.du[i] = R + exp(u) - w.rt[i];
         acc[0] += R;
         acc[7] += isfinite(R) ? 0.0 : 1.0;
@@ -311,7 +302,7 @@ __device__ void row_step(const PassArgs& A, const Ctl& c, int i, double R, doubl
     }
     case PH_GRAVE:
     case PH_Z: {
-        double u = ld_agent(A.phase == PH_GRAVE ? &w.ugrave[i] : &w.uz[i]);
+        double u = (A.phase == PH_GRAVE ? w.ugrave[i] : w.uz[i]);
         double eu = exp(u), b = R + eu, lb = log(b);
         double d = w.lrt[i] - lb;     // Greenkhorn u-step: u + log r~ - log(B1 + e^u)
         w.du[i] = d;
@@ -329,20 +320,20 @@ __device__ void col_step(const PassArgs& A, const Ctl& c, int j, double Q, doubl
     const Ws& w = A.ws;
     switch (A.phase) {
     case PH_INIT: {
-        double v = ld_agent(&w.vchk0[j]);
+        double v = w.vchk0[j];
         acc[1] += exp(v); acc[2] += w.ct[j] * v;
         acc[7] += isfinite(Q) ? 0.0 : 1.0;
         break;
     }
     case PH_BAR: {
-        double v = ld_agent(&w.vbar[j]);
+        double v = w.vbar[j];
         w.dv[j] = Q + exp(v) - w.ct[j];
         acc[7] += isfinite(Q) ? 0.0 : 1.0;
         break;
     }
     case PH_GRAVE:
     case PH_Z: {
-        double v = ld_agent(A.phase == PH_GRAVE ? &w.vgrave[j] : &w.vz[j]);
+        double v = (A.phase == PH_GRAVE ? w.vgrave[j] : w.vz[j]);
         double ev = exp(v), b = Q + ev, lb = log(b);
         double d = w.lct[j] - lb;
         w.dv[j] = d;
@@ -360,6 +351,8 @@ __device__ void col_step(const PassArgs& A, const Ctl& c, int j, double Q, doubl
 // the deciding workgroup: scalar logic of the iteration
 // ---------------------------------------------------------------------------
 // Sum the per-strip partials in a fixed order.
+// (agent-scope loads: the rounding passes gather inside the launch that
+// wrote the partials)
 __device__ void gather_strips(const double* part, int nstrips, double (&tot)[kScal], double* lds) {
 #pragma unroll
     for (int k = 0; k < kScal; ++k) tot[k] = 0.0;
@@ -397,13 +390,28 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
     double Rs[kScal], Cs[kScal];
     const bool rows = A.phase != PH_SK_COL;
     const bool cols = A.phase != PH_SK_ROW;
-    if (rows) gather_strips(A.ws.rowscal, A.ny, Rs, lds);
-    if (cols) gather_strips(A.ws.colscal, A.nx, Cs, lds);
+    {
+        // both gathers' loads in flight together, then one block reduction
+        double v[2 * kScal];
+#pragma unroll
+        for (int k = 0; k < 2 * kScal; ++k) v[k] = 0.0;
+        if (rows)
+            for (int b = threadIdx.x; b < A.nrb; b += kThreads)
+#pragma unroll
+                for (int k = 0; k < kScal; ++k) v[k] += ld_agent(&A.ws.rowscal[(int64_t)b * kScal + k]);
+        if (cols)
+            for (int b = threadIdx.x; b < A.ncb; b += kThreads)
+#pragma unroll
+                for (int k = 0; k < kScal; ++k) v[kScal + k] += ld_agent(&A.ws.colscal[(int64_t)b * kScal + k]);
+        block_sum<2 * kScal>(v, lds);
+#pragma unroll
+        for (int k = 0; k < kScal; ++k) { Rs[k] = v[k]; Cs[k] = v[kScal + k]; }
+    }
     if (threadIdx.x != 0) return;
     if (A.phase == PH_SK_ROW || A.phase == PH_SK_COL) {
         // slots 1, 2 hold per-strip (max, sum of exp): merge them in strip order
         const double* part = rows ? A.ws.rowscal : A.ws.colscal;
-        const int ns = rows ? A.ny : A.nx;
+        const int ns = rows ? A.nrb : A.ncb;
         double mx = -INFINITY, se = 0.0;
         for (int k = 0; k < ns; ++k)
             lse_merge(mx, se, ld_agent(&part[(int64_t)k * kScal + 1]), ld_agent(&part[(int64_t)k * kScal + 2]));
@@ -596,131 +604,140 @@ template <int KIND, bool ROWS, bool COLS>
 __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     constexpr int VW = (KIND == POT_COST_BF16) ? 8 : 4;
     constexpr bool PTS = (KIND == POT_COST_SQEUCLID_POINTS);
+    constexpr int EB = (KIND == POT_COST_BF16) ? 2 : 4;      // bytes per stored cost
+    constexpr int U = 4;                                     // rows per load batch
     __shared__ double s_a[kMaxBR];         // row offsets (log2 units, tile shift folded in)
-    __shared__ double s_x[PTS ? kMaxBR * 3 : 1];   // points: source coordinates (FP64)
-    __shared__ double s_red[64];
-    __shared__ int s_flags[4];
-    __shared__ int s_K;
-    __shared__ int s_kmx[4];
+    __shared__ double s_b[kMaxBC];         // column offsets (log2 units)
+    __shared__ double s_x[PTS ? kMaxBR * 3 : 1];   // points: source coordinates - tile origin (FP64)
+    __shared__ double s_y[PTS ? 256 * 3 : 1];      // points (BC = 256): 2 G (target coordinates - tile origin)
+    __shared__ double s_lvl[4];
     // one 16 KB buffer reused by the phases of the kernel:
     //   sweep:     per-lane row partials of a 64-row chunk, float [4][16][64]
     //   columns:   column partials of the 4 waves, double [4][BC]
-    //   finalise:  strip sums, double [kMaxBR] (rows) and [kMaxBC] (columns)
     __shared__ __align__(16) double s_buf[2048];
     float (*s_rowp)[16][64] = reinterpret_cast<float (*)[16][64]>(s_buf);
     double* s_col = s_buf;                 // [4][bc]
-    double* s_R = s_buf;                   // [br]
-    double* s_Q = s_buf + kMaxBR;          // [bc]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = blockIdx.x;
+    const int ty = tile % A.ny, tx = tile / A.ny;
+    const int i0 = ty * A.br, j0 = tx * A.bc;
+    const int rows = min(A.br, A.n - i0), cols = min(A.bc, A.m - j0);
+    const int jg = j0 + lane * VW;         // this lane's first column
+
+    // ---- interior tiles: the first batch of costs is loaded while the
+    // prologue computes the point of the pass (a converged solve exits
+    // below; the hardware drains outstanding loads at the end of a wave)
+    const bool vec_ok = !PTS && ((A.ldc % VW) == 0) && ((((uintptr_t)A.C) & 15) == 0);
+    const bool fast = (PTS || vec_ok) && rows == A.br && (A.br % 64) == 0 && j0 + A.bc <= A.m;
+    const char* cbase = (const char*)A.C + ((int64_t)(i0 + wave) * A.ldc + jg) * EB;   // row i0 + wave
+    const int64_t rstep = (int64_t)4 * A.ldc * EB;                                      // 4 rows down
+    float4 pre[U];
+    if (!PTS && fast) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) pre[u] = *(const float4*)(cbase + u * rstep);
+    }
+    // candidate state of this thread's row (tid) and columns (tid, tid + 256)
+    const SideVecs RV = side_vecs(A, 0), CV = side_vecs(A, 1);
+    Cand rq = {0.0, 0.0, 0.0, 0.0, 0.0}, cq[2] = {rq, rq};
+    if (tid < rows) rq = load_cand(A, RV, 0, i0 + tid);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (tid + h * kThreads < cols) cq[h] = load_cand(A, CV, 1, j0 + tid + h * kThreads);
+    int K = A.ws.tshift[tile];             // this tile's shift, kept from its previous pass
 
     Ctl& c = *A.ws.ctl;
     if (c.done) return;                     // converged earlier: nothing to do
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ty = blockIdx.x % A.ny, tx = blockIdx.x / A.ny;
-    const int i0 = ty * A.br, j0 = tx * A.bc;
-    const int rows = min(A.br, A.n - i0), cols = min(A.bc, A.m - j0);
-
-    // ---- prologue: the point of this pass on this tile's rows and columns
+    // ---- prologue: the point of this pass on this tile's rows and columns,
+    // in log2 units; the duals are clamped to +-2^29 so that every exponent
+    // below fits the split of exp2_split (|G * C| < 2^29 is checked on the host)
+    const double G = c.G;
     const double wp = w_point(A, c);
-    if (tid == 0) s_K = -100000;
-    __syncthreads();
-    for (int r = tid; r < rows; r += kThreads) {
-        double u = row_point(A, c, i0 + r, tx == 0);
-        s_a[r] = (u + wp) * kLog2e;
-        if (PTS) {
-            for (int k = 0; k < 3; ++k) s_x[r * 3 + k] = k < A.d ? (double)A.x[(int64_t)(i0 + r) * A.d + k] : 0.0;
-        }
-        atomicMax(&s_K, ilogb(A.ws.rt[i0 + r]));    // tile shift: sums kept near 2^0
+    constexpr double kClamp = 536870912.0;  // 2^29
+    double ox[3] = {0.0, 0.0, 0.0};        // points: tile origin (first source point)
+    if (PTS) {
+        for (int k = 0; k < A.d; ++k) ox[k] = (double)A.x[(int64_t)i0 * A.d + k];
     }
-    // each thread's VW columns
-    const int jg = j0 + lane * VW;
+    if (tid < rows) {
+        double a = fmin(fmax((eval_point(A, c, RV, rq, 0, i0 + tid, tx == 0) + wp) * kLog2e, -kClamp), kClamp);
+        if (PTS) {
+            // t_ij = a_i + b_j - G |x_i - y_j|^2, with x, y taken relative to the
+            // origin o: (a_i - G|x_i - o|^2) + (b_j - G|y_j - o|^2) + 2G (x_i - o).(y_j - o)
+            double xx = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double xk = k < A.d ? (double)A.x[(int64_t)(i0 + tid) * A.d + k] - ox[k] : 0.0;
+                s_x[tid * 3 + k] = xk;
+                xx += xk * xk;
+            }
+            a -= G * xx;
+        }
+        s_a[tid] = a - (double)K;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = tid + h * kThreads;
+        if (q < cols) {
+            const int j = j0 + q;
+            double v = fmin(fmax(eval_point(A, c, CV, cq[h], 1, j, ty == 0) * kLog2e, -kClamp), kClamp);
+            if (PTS) {
+                double yy = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double yk = k < A.d ? (double)A.y[(int64_t)j * A.d + k] - ox[k] : 0.0;
+                    s_y[q * 3 + k] = 2.0 * G * yk;
+                    yy += yk * yk;
+                }
+                v -= G * yy;
+            }
+            s_b[q] = v;
+        }
+    }
+    __syncthreads();
+    // this lane's VW columns (masked columns get 0 and e = 0 below)
     double b[VW];
     double y2[VW][3];
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
-        int j = jg + k;
-        y2[k][0] = y2[k][1] = y2[k][2] = 0.0;
-        if (j < A.m && lane * VW + k < A.bc) {
-            double v = col_point(A, c, j, ty == 0 && wave == 0);
-            b[k] = v * kLog2e;
-            if (PTS) {
-                // t_ij = a_i + b_j - G |x_i - y_j|^2 = (a_i - G|x_i|^2) + (b_j - G|y_j|^2) + 2G x_i.y_j
-                double yy = 0.0;
-                for (int q = 0; q < A.d; ++q) {
-                    double yq = (double)A.y[(int64_t)j * A.d + q];
-                    y2[k][q] = 2.0 * c.G * yq;
-                    yy += yq * yq;
-                }
-                b[k] -= c.G * yy;
-            }
-        } else {
-            b[k] = 0.0;    // masked below (e = 0)
-        }
+        const int q = lane * VW + k;
+        const bool in = jg + k < A.m;
+        b[k] = in ? s_b[q] : 0.0;
+        y2[k][0] = PTS && in ? s_y[q * 3] : 0.0;
+        y2[k][1] = PTS && in ? s_y[q * 3 + 1] : 0.0;
+        y2[k][2] = PTS && in ? s_y[q * 3 + 2] : 0.0;
     }
-    __syncthreads();
-    const int K = s_K;
-    const double shift = (double)K;
-    for (int r = tid; r < rows; r += kThreads) {
-        double a = s_a[r] - shift;
-        if (PTS) {
-            double xx = 0.0;
-            for (int k = 0; k < A.d; ++k) xx += s_x[r * 3 + k] * s_x[r * 3 + k];
-            a -= c.G * xx;
-        }
-        s_a[r] = a;
-    }
-    __syncthreads();
-    const double G = c.G;
     const float Gf = (float)G;
     float bf[VW];
 #pragma unroll
     for (int k = 0; k < VW; ++k) bf[k] = (float)b[k];
-    const bool full = jg + VW <= A.m;   // masked columns only in the last column strip
 
-    // ---- tile.  A sweep forms every term of the tile, accumulates the column
-    // partials (FP32 over a batch of U rows, then FP64) and per-lane row
-    // partials, which are reduced through LDS once per chunk of 64 rows.  It
-    // also returns the largest binary exponent of its terms: if that is out of
-    // [-60, 60] (all terms tiny, or some huge: far-apart points at the start,
-    // extrapolated ASPOT points), the tile is swept again with its shift moved
-    // by that exponent so FP32 holds the dominant terms; the FP64 partials
-    // carry the shift's scale.
+    // ---- tile.  A sweep forms every term 2^t of the tile, accumulates the
+    // column partials (FP32 over a batch of U rows, then FP64) and per-lane
+    // row partials, reduced through LDS once per chunk of 64 rows.  It returns
+    // the tile's level: the largest row or column sum relative to the shift.
+    // A level outside [2^-60, 2^60] (far-apart points, tiny or huge duals at
+    // extrapolated ASPOT points) moves the shift and sweeps again; the shift
+    // is kept for the tile's next pass, so a far tile re-sweeps once per solve.
     double colacc[VW];
-    const bool vec_ok = !PTS && ((A.ldc % VW) == 0) && ((((uintptr_t)A.C) & 15) == 0);
-    // interior tile: every row and column in range, aligned rows -> branch-free loads
-    const bool fast = vec_ok && rows == A.br && (A.br % 64) == 0 && j0 + A.bc <= A.m;
-    constexpr int U = 4;
 
-    // one row of VW terms: exponent, 2^t, row and column accumulation
-    auto row_terms = [&](const float* cvals, int r, double a, float* col32, int& kmx, float& tmx) -> float {
+    // terms of one row: returns the row's lane partial and adds to col32
+    auto row_terms = [&](auto full_tag, const float* cv, int r, double a, float* col32) -> float {
+        constexpr bool FULL = decltype(full_tag)::value;
         float e[VW];
-        if (PTS) {
+        if constexpr (PTS) {
             const double x0 = s_x[r * 3], x1 = s_x[r * 3 + 1], x2 = s_x[r * 3 + 2];
 #pragma unroll
-            for (int k = 0; k < VW; ++k) {
-                int kk;
-                double t = fma(x0, y2[k][0], fma(x1, y2[k][1], fma(x2, y2[k][2], a + b[k])));
-                e[k] = exp2_split(t, kk);
-                kmx = max(kmx, full ? kk : ((jg + k < A.m) ? kk : -1000000));
-            }
-        } else if (KIND == POT_COST_BF16) {
+            for (int k = 0; k < VW; ++k)
+                e[k] = exp2_split(fma(x0, y2[k][0], fma(x1, y2[k][1], fma(x2, y2[k][2], a + b[k]))));
+        } else if constexpr (KIND == POT_COST_BF16) {
             // BF16 costs: FP32 exponent (the BF16 rounding of C dominates its error)
             const float af = (float)a;
 #pragma unroll
-            for (int k = 0; k < VW; ++k) {
-                float t = fmaf(cvals[k], -Gf, af + bf[k]);
-                e[k] = __builtin_amdgcn_exp2f(t);
-                tmx = fmaxf(tmx, (full || jg + k < A.m) ? t : -INFINITY);
-            }
+            for (int k = 0; k < VW; ++k) e[k] = __builtin_amdgcn_exp2f(fmaf(cv[k], -Gf, af + bf[k]));
         } else {
 #pragma unroll
-            for (int k = 0; k < VW; ++k) {
-                int kk;
-                e[k] = exp2_split(fma((double)cvals[k], -G, a + b[k]), kk);
-                kmx = max(kmx, full ? kk : ((jg + k < A.m) ? kk : -1000000));
-            }
+            for (int k = 0; k < VW; ++k) e[k] = exp2_split(fma((double)cv[k], -G, a + b[k]));
         }
-        if (!full) {
+        if constexpr (!FULL) {
 #pragma unroll
             for (int k = 0; k < VW; ++k) e[k] = (jg + k < A.m) ? e[k] : 0.0f;
         }
@@ -733,67 +750,75 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         return rs;
     };
 
-    // reduce the per-lane row partials of a 64-row chunk and write them
-    auto emit_rows = [&](int c0, double scale_d) {
+    // reduce the per-lane row partials of a 64-row chunk; write them; level
+    auto emit_rows = [&](int c0, double scale_d, double& lvl) {
         __syncthreads();
-        if (ROWS) {
-            const int rl = tid >> 2, q = tid & 3;          // row of the chunk, quarter of the lanes
-            const int wv = rl & 3, slot = rl >> 2;         // row rl = wave wv's slot-th row
-            double sacc = 0.0;
+        const int rl = tid >> 2, q = tid & 3;          // row of the chunk, quarter of the lanes
+        const int wv = rl & 3, slot = rl >> 2;         // row rl = wave wv's slot-th row
+        double sacc = 0.0;
 #pragma unroll
-            for (int l = 0; l < 16; ++l) sacc += (double)s_rowp[wv][slot][q * 16 + l];
-            sacc += __shfl_xor(sacc, 1, 64);
-            sacc += __shfl_xor(sacc, 2, 64);
-            const int r = c0 + rl;
-            if (q == 0 && r < rows) st_agent(&((double*)A.ws.rowpart)[(int64_t)tx * A.n + i0 + r], sacc * scale_d);
+        for (int l = 0; l < 16; ++l) sacc += (double)s_rowp[wv][slot][q * 16 + l];
+        sacc += __shfl_xor(sacc, 1, 64);
+        sacc += __shfl_xor(sacc, 2, 64);
+        const int r = c0 + rl;
+        if (r < rows) {
+            lvl = fmax(lvl, sacc);                     // (NaN sums reach the finalisers' check)
+            if (ROWS && q == 0) ((double*)A.ws.rowpart)[(int64_t)tx * A.n + i0 + r] = sacc * scale_d;
         }
         __syncthreads();
     };
 
-    auto sweep = [&](double scale_d) -> int {
-        int kmx = -1000000;
-        float tmx = -INFINITY;   // BF16 path: largest FP32 exponent
+    auto sweep = [&](bool use_pre, double scale_d) -> double {
+        double lvl = 0.0;
 #pragma unroll
         for (int k = 0; k < VW; ++k) colacc[k] = 0.0;
         for (int c0 = 0; c0 < rows; c0 += 64) {
             // this wave's rows of the chunk: c0 + wave + 4 * slot, slot = 0..15
             if (fast) {
-                using VT = float4;   // 16 bytes: 4 FP32 or 8 BF16 costs
-                const char* p0 = (const char*)A.C +
-                                 ((int64_t)(i0 + c0 + wave) * A.ldc + jg) * (KIND == POT_COST_BF16 ? 2 : 4);
-                const int64_t rstep = 4 * A.ldc * (KIND == POT_COST_BF16 ? 2 : 4);
-                VT cur[U], nxt[U];
+                float4 cur[U], nxt[U];
+                if (!PTS) {
+                    if (use_pre && c0 == 0) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) cur[u] = *(const VT*)(p0 + u * rstep);
+                        for (int u = 0; u < U; ++u) cur[u] = pre[u];
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) cur[u] = *(const float4*)(cbase + ((int64_t)c0 / 4 + u) * rstep);
+                    }
+                }
 #pragma unroll
                 for (int bb = 0; bb < 16 / U; ++bb) {
-                    if (bb + 1 < 16 / U) {
+                    if (!PTS && bb + 1 < 16 / U) {
 #pragma unroll
-                        for (int u = 0; u < U; ++u) nxt[u] = *(const VT*)(p0 + ((bb + 1) * U + u) * rstep);
+                        for (int u = 0; u < U; ++u)
+                            nxt[u] = *(const float4*)(cbase + ((int64_t)c0 / 4 + (bb + 1) * U + u) * rstep);
                     }
+                    double av[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) av[u] = s_a[c0 + wave + 4 * (bb * U + u)];
                     float col32[VW];
 #pragma unroll
                     for (int k = 0; k < VW; ++k) col32[k] = 0.0f;
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int slot = bb * U + u, r = c0 + wave + 4 * slot;
-                        float cvals[VW];
-                        if (KIND == POT_COST_BF16) {
+                        float cv[VW];
+                        if constexpr (KIND == POT_COST_BF16) {
                             const uint32_t w4[4] = {__float_as_uint(cur[u].x), __float_as_uint(cur[u].y),
                                                     __float_as_uint(cur[u].z), __float_as_uint(cur[u].w)};
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
-                                cvals[2 * k] = __uint_as_float(w4[k] << 16);
-                                cvals[2 * k + 1] = __uint_as_float(w4[k] & 0xffff0000u);
+                                cv[2 * k] = __uint_as_float(w4[k] << 16);
+                                cv[2 * k + 1] = __uint_as_float(w4[k] & 0xffff0000u);
                             }
-                        } else {
-                            cvals[0] = cur[u].x; cvals[1] = cur[u].y; cvals[2] = cur[u].z; cvals[3] = cur[u].w;
+                        } else if constexpr (KIND == POT_COST_F32) {
+                            cv[0] = cur[u].x; cv[1] = cur[u].y; cv[2] = cur[u].z; cv[3] = cur[u].w;
                         }
-                        s_rowp[wave][slot][lane] = row_terms(cvals, r, s_a[r], col32, kmx, tmx);
+                        s_rowp[wave][slot][lane] =
+                            row_terms(std::integral_constant<bool, true>{}, cv, r, av[u], col32);
                     }
 #pragma unroll
                     for (int k = 0; k < VW; ++k) colacc[k] += (double)col32[k];
-                    if (bb + 1 < 16 / U) {
+                    if (!PTS && bb + 1 < 16 / U) {
 #pragma unroll
                         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
                     }
@@ -803,46 +828,87 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
                     const int r = c0 + wave + 4 * slot;
                     float rs = 0.0f;
                     if (r < rows) {
-                        float cvals[VW];
-                        if (!PTS) {
-                            if (jg < A.m) load_costs<KIND>(A, i0 + r, jg, vec_ok, cvals);
-                            else {
+                        float cv[VW];
 #pragma unroll
-                                for (int k = 0; k < VW; ++k) cvals[k] = 0.0f;
-                            }
-                        }
+                        for (int k = 0; k < VW; ++k) cv[k] = 0.0f;
+                        if (!PTS && jg < A.m) load_costs<KIND>(A, i0 + r, jg, vec_ok, cv);
                         float col32[VW];
 #pragma unroll
                         for (int k = 0; k < VW; ++k) col32[k] = 0.0f;
-                        rs = row_terms(cvals, r, s_a[r], col32, kmx, tmx);
+                        rs = row_terms(std::integral_constant<bool, false>{}, cv, r, s_a[r], col32);
 #pragma unroll
                         for (int k = 0; k < VW; ++k) colacc[k] += (double)col32[k];
                     }
                     s_rowp[wave][slot][lane] = rs;
                 }
             }
-            emit_rows(c0, scale_d);
+            emit_rows(c0, scale_d, lvl);
         }
-        if (KIND == POT_COST_BF16 && tmx > -INFINITY)
-            kmx = (int)floorf(fmaxf(fminf(tmx, 1.0e6f), -1.0e6f));
-        return kmx;
-    };
-    double scale_d = ldexp(1.0, K);
-    int kmx = sweep(scale_d);
-    // block max of the terms' exponents
-    {
+        if (COLS) {
+            // the level also covers this thread's column sums
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) kmx = max(kmx, __shfl_xor(kmx, o, 64));
-        if (lane == 0) s_kmx[wave] = kmx;
+            for (int k = 0; k < VW; ++k) lvl = fmax(lvl, colacc[k]);
+        }
+        return lvl;
+    };
+
+    // largest exponent of the tile's terms (used only when every sum of the
+    // tile under- or overflowed, so the level says nothing)
+    auto max_exponent = [&]() -> double {
+        double mx = -INFINITY;
+        for (int r = wave; r < rows; r += 4) {
+            float cv[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) cv[k] = 0.0f;
+            if (!PTS && jg < A.m) load_costs<KIND>(A, i0 + r, jg, vec_ok, cv);
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                double t;
+                if (PTS) t = fma(s_x[r * 3], y2[k][0], fma(s_x[r * 3 + 1], y2[k][1], fma(s_x[r * 3 + 2], y2[k][2], s_a[r] + b[k])));
+                else t = fma((double)cv[k], -G, s_a[r] + b[k]);
+                if (jg + k < A.m) mx = fmax(mx, t);
+            }
+        }
+        return mx;
+    };
+
+    auto block_level = [&](double v) -> double {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        if (lane == 0) s_lvl[wave] = v;
         __syncthreads();
-        kmx = max(max(s_kmx[0], s_kmx[1]), max(s_kmx[2], s_kmx[3]));
+        double l = fmax(fmax(s_lvl[0], s_lvl[1]), fmax(s_lvl[2], s_lvl[3]));
         __syncthreads();
-    }
-    if (kmx > -1000000 && (kmx > 60 || kmx < -60)) {
-        for (int r = tid; r < rows; r += kThreads) s_a[r] -= (double)kmx;
-        __syncthreads();
-        scale_d = ldexp(1.0, K + kmx);
-        sweep(scale_d);
+        return l;
+    };
+
+    double scale_d = ldexp(1.0, K);
+    double lvl = block_level(sweep(true, scale_d));
+    const double kHi = 1.152921504606846976e18;   // 2^60
+    const double kLo = 8.673617379884035472e-19;  // 2^-60
+    if (!(lvl <= kHi && lvl >= kLo)) {
+        int delta;
+        if (lvl > 0.0 && lvl < INFINITY) delta = ilogb(lvl);
+        else {
+            // every sum flushed to 0 or overflowed: locate the largest term
+            double mx = max_exponent();
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            if (lane == 0) s_lvl[wave] = mx;
+            __syncthreads();
+            mx = fmax(fmax(s_lvl[0], s_lvl[1]), fmax(s_lvl[2], s_lvl[3]));
+            __syncthreads();
+            delta = isfinite(mx) ? (int)floor(mx) : 0;
+        }
+        delta = max(-2000 - K, min(2000 - K, delta));
+        if (delta != 0) {
+            for (int r = tid; r < rows; r += kThreads) s_a[r] -= (double)delta;
+            K += delta;
+            __syncthreads();
+            scale_d = ldexp(1.0, K);
+            sweep(false, scale_d);
+            if (tid == 0) A.ws.tshift[tile] = K;
+        }
     }
     if (COLS) {
 #pragma unroll
@@ -851,78 +917,82 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         for (int q = tid; q < cols; q += kThreads) {
             const int B = 64 * VW;
             double v = (s_col[q] + s_col[B + q]) + (s_col[2 * B + q] + s_col[3 * B + q]);
-            st_agent(&((double*)A.ws.colpart)[(int64_t)ty * A.m + j0 + q], v * scale_d);
+            ((double*)A.ws.colpart)[(int64_t)ty * A.m + j0 + q] = v * scale_d;
         }
     }
 
-    // ---- arrival: the last WG of a strip finalises it
+}
+
+// ---------------------------------------------------------------------------
+// the finalising pass: after the tile pass (the kernel boundary orders its
+// partials), each workgroup reduces the partials of 64 rows (or 64 columns)
+// in FP64, applies the per-row (per-column) step of the algorithm and writes
+// its block's sums; the last block to arrive makes the iteration's scalar
+// decisions.
+// ---------------------------------------------------------------------------
+constexpr int kFinBlock = 64;
+
+__global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
+    __shared__ double s_part[4][kFinBlock];
+    __shared__ double s_v[kFinBlock];
+    __shared__ double s_red[64];
+    __shared__ int s_last;
+    Ctl& c = *A.ws.ctl;
+    if (c.done) return;
+    const int tid = threadIdx.x;
+    const bool rows_pass = A.phase != PH_SK_COL;
+    const int blk = blockIdx.x;
+    const bool is_row = rows_pass && blk < A.nrb;
+    const int cb = rows_pass ? blk - A.nrb : blk;      // column block index
+    const int base = is_row ? blk * kFinBlock : cb * kFinBlock;
+    const int len = min(kFinBlock, (is_row ? A.n : A.m) - base);
+    // sum of the tile partials: 4 threads per row (column), each a quarter of
+    // the strips, combined in a fixed order
+    {
+        const int l = tid & (kFinBlock - 1), q = tid / kFinBlock;
+        double acc = 0.0;
+        if (l < len) {
+            if (is_row) {
+                const double* p = (const double*)A.ws.rowpart + base + l;
+#pragma unroll 4
+                for (int x = q; x < A.nx; x += 4) acc += p[(int64_t)x * A.n];
+            } else {
+                const double* p = (const double*)A.ws.colpart + base + l;
+#pragma unroll 4
+                for (int y = q; y < A.ny; y += 4) acc += p[(int64_t)y * A.m];
+            }
+        }
+        s_part[q][l] = acc;
+        __syncthreads();
+        if (tid < kFinBlock) s_v[tid] = (s_part[0][tid] + s_part[1][tid]) + (s_part[2][tid] + s_part[3][tid]);
+        __syncthreads();
+    }
+    double* out = (is_row ? A.ws.rowscal + (int64_t)blk * kScal : A.ws.colscal + (int64_t)cb * kScal);
+    if (A.phase == PH_SK_ROW) {
+        sk_row_finalise(A, c, base, len, s_v, out, s_red);
+    } else if (A.phase == PH_SK_COL) {
+        sk_col_finalise(A, c, base, len, s_v, out, s_red);
+    } else {
+        double acc[kScal];
+#pragma unroll
+        for (int k = 0; k < kScal; ++k) acc[k] = 0.0;
+        if (tid < len) {
+            if (is_row) row_step(A, c, base + tid, s_v[tid], acc);
+            else col_step(A, c, base + tid, s_v[tid], acc);
+        }
+        block_sum<kScal>(acc, s_red);
+        if (tid == 0)
+            for (int k = 0; k < kScal; ++k) st_agent(&out[k], acc[k]);
+    }
+    // arrival: the last block decides
     wait_stores();
     __syncthreads();
-    if (tid == 0) {
-        s_flags[0] = ROWS ? (atomicAdd(&A.ws.rowcnt[ty], 1) == A.nx - 1) : 0;
-        s_flags[1] = COLS ? (atomicAdd(&A.ws.colcnt[tx], 1) == A.ny - 1) : 0;
-    }
+    const int total = (rows_pass ? A.nrb : 0) + (A.phase != PH_SK_ROW ? A.ncb : 0);
+    if (tid == 0) s_last = (atomicAdd(&A.ws.glob[0], 1) == total - 1);
     __syncthreads();
-    int nfin = 0;
-    if (ROWS && s_flags[0]) {
-        // R_i = sum over column strips of the partials, in FP64
-        for (int r = tid; r < rows; r += kThreads) {
-            double R = 0.0;
-            const double* p = (const double*)A.ws.rowpart + i0 + r;
-#pragma unroll 8
-            for (int x = 0; x < A.nx; ++x) R += ld_agent(&p[(int64_t)x * A.n]);
-            s_R[r] = R;
-        }
-        __syncthreads();
-        double* out = A.ws.rowscal + (int64_t)ty * kScal;
-        if (A.phase == PH_SK_ROW) {
-            sk_row_finalise(A, c, i0, rows, s_R, out, s_red);
-        } else {
-            double acc[kScal];
-#pragma unroll
-            for (int k = 0; k < kScal; ++k) acc[k] = 0.0;
-            for (int r = tid; r < rows; r += kThreads) row_step(A, c, i0 + r, s_R[r], acc);
-            block_sum<kScal>(acc, s_red);
-            if (tid == 0)
-                for (int k = 0; k < kScal; ++k) st_agent(&out[k], acc[k]);
-        }
-        if (tid == 0) A.ws.rowcnt[ty] = 0;
-        ++nfin;
-    }
-    if (COLS && s_flags[1]) {
-        for (int q = tid; q < cols; q += kThreads) {
-            double Q = 0.0;
-            const double* p = (const double*)A.ws.colpart + j0 + q;
-#pragma unroll 8
-            for (int y = 0; y < A.ny; ++y) Q += ld_agent(&p[(int64_t)y * A.m]);
-            s_Q[q] = Q;
-        }
-        __syncthreads();
-        double* out = A.ws.colscal + (int64_t)tx * kScal;
-        if (A.phase == PH_SK_COL) {
-            sk_col_finalise(A, c, j0, cols, s_Q, out, s_red);
-        } else {
-            double acc[kScal];
-#pragma unroll
-            for (int k = 0; k < kScal; ++k) acc[k] = 0.0;
-            for (int q = tid; q < cols; q += kThreads) col_step(A, c, j0 + q, s_Q[q], acc);
-            block_sum<kScal>(acc, s_red);
-            if (tid == 0)
-                for (int k = 0; k < kScal; ++k) st_agent(&out[k], acc[k]);
-        }
-        if (tid == 0) A.ws.colcnt[tx] = 0;
-        ++nfin;
-    }
-    if (nfin) {
-        wait_stores();
-        __syncthreads();
-        const int total = (ROWS ? A.ny : 0) + (COLS ? A.nx : 0);
-        if (tid == 0) s_flags[2] = (atomicAdd(&A.ws.glob[0], nfin) + nfin == total);
-        __syncthreads();
-        if (s_flags[2]) {
-            decide(A, c, s_red);
-            if (tid == 0) A.ws.glob[0] = 0;
-        }
+    if (s_last) {
+        decide(A, c, s_red);
+        if (tid == 0) A.ws.glob[0] = 0;
     }
 }
 
@@ -1200,6 +1270,7 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
         for (int j = tid; j < S.m; j += nt) S.ws.vz[j] = 0.0;
     }
     for (int k = tid; k < S.ny; k += nt) S.ws.rowcnt[k] = 0;
+    for (int k = tid; k < S.nx * S.ny; k += nt) S.ws.tshift[k] = 0;
     for (int k = tid; k < S.nx; k += nt) S.ws.colcnt[k] = 0;
     if (tid < 4) S.ws.glob[tid] = 0;
     if (tid == 0) {
@@ -1327,9 +1398,14 @@ __global__ void copy_out(PassArgs A, double* alpha, double* beta, double* pp, do
 // ---------------------------------------------------------------------------
 hipError_t launch_setup(const SetupArgs& S, hipStream_t st);
 
+static int fin_blocks(const PassArgs& A) {
+    return (A.phase != PH_SK_COL ? A.nrb : 0) + (A.phase != PH_SK_ROW ? A.ncb : 0);
+}
+
 template <int KIND, bool ROWS, bool COLS>
 static hipError_t launch_stats_k(const PassArgs& A, hipStream_t st) {
     stats_pass<KIND, ROWS, COLS><<<A.nx * A.ny, kThreads, 0, st>>>(A);
+    fin_pass<<<fin_blocks(A), kThreads, 0, st>>>(A);
     return hipGetLastError();
 }
 
@@ -1351,16 +1427,20 @@ hipError_t launch_stats(const PassArgs& A, hipStream_t st) {
 // Timed launch of the statistics pass: start/stop events recorded around the
 // dispatch itself (not around the host call).
 template <int KIND>
-static hipError_t launch_stats_timed_k(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+static hipError_t launch_stats_timed_k(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                                       hipEvent_t e2, hipEvent_t e3) {
     hipExtLaunchKernelGGL((stats_pass<KIND, true, true>), dim3(A.nx * A.ny), dim3(kThreads), 0, st, e0, e1, 0, A);
+    hipExtLaunchKernelGGL(fin_pass, dim3(fin_blocks(A)), dim3(kThreads), 0, st, e2, e3, 0, A);
     return hipGetLastError();
 }
 
-hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+// Both kernels of one pass, each with start/stop events around its dispatch.
+hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
+                              hipEvent_t e3) {
     switch (A.kind) {
-    case POT_COST_F32: return launch_stats_timed_k<POT_COST_F32>(A, st, e0, e1);
-    case POT_COST_BF16: return launch_stats_timed_k<POT_COST_BF16>(A, st, e0, e1);
-    default: return launch_stats_timed_k<POT_COST_SQEUCLID_POINTS>(A, st, e0, e1);
+    case POT_COST_F32: return launch_stats_timed_k<POT_COST_F32>(A, st, e0, e1, e2, e3);
+    case POT_COST_BF16: return launch_stats_timed_k<POT_COST_BF16>(A, st, e0, e1, e2, e3);
+    default: return launch_stats_timed_k<POT_COST_SQEUCLID_POINTS>(A, st, e0, e1, e2, e3);
     }
 }
 

@@ -25,7 +25,7 @@ _LIB = os.path.join(HERE, "libpot.so")
 
 ASPOT, SINKHORN = 0, 1
 COST_F32, COST_BF16, COST_POINTS = 0, 1, 3
-FLAG_WANT_PLAN, FLAG_NO_ROUND = 1, 2
+FLAG_WANT_PLAN, FLAG_NO_ROUND, FLAG_NO_GRAPH = 1, 2, 4
 
 OK, ERR_INVALID_ARG, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_WORKSPACE, ERR_UNSUPPORTED = range(7)
 
@@ -97,7 +97,7 @@ def load():
                                       ct.POINTER(ct.c_void_p), ct.c_void_p]
     lib.pot_solve_batched.restype = ct.c_int
     lib.pot_time_pass.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
-                                  ct.c_int32, ct.POINTER(ct.c_double), ct.c_void_p]
+                                  ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.c_void_p]
     lib.pot_time_pass.restype = ct.c_int
     lib.pot_status_string.argtypes = [ct.c_int]
     lib.pot_status_string.restype = ct.c_char_p
@@ -212,8 +212,9 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     if trace_cap > 0:
         tr_i = torch.full((trace_cap * 3,), -9, dtype=torch.int32, device=dev)
         tr_d = torch.full((trace_cap * 4,), float("nan"), dtype=torch.float64, device=dev)
-    opts = make_options(eps, algo=algo, flags=(FLAG_WANT_PLAN if want_plan else 0), trace_i=tr_i,
-                        trace_d=tr_d, trace_cap=trace_cap, **opt_kw)
+    flags = (FLAG_WANT_PLAN if want_plan else 0) | int(opt_kw.pop("flags", 0))
+    opts = make_options(eps, algo=algo, flags=flags, trace_i=tr_i, trace_d=tr_d, trace_cap=trace_cap,
+                        **opt_kw)
     nbytes = workspace_bytes(prob, opts)
     if nbytes == 0:
         raise PotError(ERR_INVALID_ARG, "invalid sizes")
@@ -313,8 +314,9 @@ def to_device_instance(inst, device="cuda", kind="f32", pad_ldc=False):
 
 def time_pass(r, c, s, eps, reps=50, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=0.0,
               cmax=1.0, u0=None, v0=None, w0=0.0, stream=None, tile_rows=0):
-    """Mean kernel time (ms) of the fused statistics pass at (u0, v0, w0),
-    from HIP events recorded around each dispatch (pot_time_pass)."""
+    """Mean kernel times (ms) of the statistics pass at (u0, v0, w0), from
+    HIP events recorded around each dispatch (pot_time_pass): returns
+    (tile kernel, finalising kernel)."""
     import torch
     lib = load()
     prob = make_problem(r, c, s, C=C, x=x, y=y, kind=kind, ldc=ldc, cost_scale=cost_scale, cmax=cmax)
@@ -323,8 +325,9 @@ def time_pass(r, c, s, eps, reps=50, C=None, x=None, y=None, kind=None, ldc=None
     ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=r.device)
     aligned = (ws.data_ptr() + 255) & ~255
     ms = ct.c_double(0.0)
+    ms2 = ct.c_double(0.0)
     st = lib.pot_time_pass(ct.byref(prob), ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(nbytes),
-                           int(reps), ct.byref(ms), _stream_ptr(stream))
+                           int(reps), ct.byref(ms), ct.byref(ms2), _stream_ptr(stream))
     if st != OK:
         raise PotError(st, last_error())
-    return ms.value
+    return ms.value, ms2.value
