@@ -25,37 +25,76 @@ namespace pot {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Wave reductions with DPP lane moves (VALU only; no LDS round trips).  A
+// double moves as its two 32-bit halves.  `old` is what lanes outside the
+// row mask receive.  Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v, double old) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f(float v, float old) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+constexpr int kQuadX1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int kQuadX2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int kHalfMirror = 0x141; // row_half_mirror
+constexpr int kMirror = 0x140;     // row_mirror
+constexpr int kBcast15 = 0x142;    // row_bcast:15 (lane 15 of a row into the next row)
+constexpr int kBcast31 = 0x143;    // row_bcast:31 (lane 31 into rows 2 and 3)
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
+// fixed combination order: deterministic; the total is returned to every lane
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_d<kQuadX1>(v, 0.0);
+    v += dpp_d<kQuadX2>(v, 0.0);
+    v += dpp_d<kHalfMirror>(v, 0.0);
+    v += dpp_d<kMirror>(v, 0.0);            // every lane: its row's sum
+    v += dpp_d<kBcast15, 0xA>(v, 0.0);      // rows 1, 3 add rows 0, 2
+    v += dpp_d<kBcast31, 0xC>(v, 0.0);      // rows 2, 3 add rows 0 + 1
+    return readlane_d(v, 63);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f<kQuadX1>(v, 0.0f);
+    v += dpp_f<kQuadX2>(v, 0.0f);
+    v += dpp_f<kHalfMirror>(v, 0.0f);
+    v += dpp_f<kMirror>(v, 0.0f);
+    v += dpp_f<kBcast15, 0xA>(v, 0.0f);
+    v += dpp_f<kBcast31, 0xC>(v, 0.0f);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_d<kQuadX1>(v, v));
+    v = fmax(v, dpp_d<kQuadX2>(v, v));
+    v = fmax(v, dpp_d<kHalfMirror>(v, v));
+    v = fmax(v, dpp_d<kMirror>(v, v));
+    v = fmax(v, dpp_d<kBcast15, 0xA>(v, v));
+    v = fmax(v, dpp_d<kBcast31, 0xC>(v, v));
+    return readlane_d(v, 63);
 }
 
 // Sum K doubles over the 256 threads of the block (fixed order: deterministic).
-// Result valid in thread 0 (returned to all threads via LDS).
+// The result is returned to every thread.
 template <int K>
 __device__ void block_sum(double (&v)[K], double* lds /* >= 4*K */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = wave_sum(v[k]);
-        if (lane == 0) lds[wave * K + k] = s;
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = lds[k] + lds[K + k] + lds[2 * K + k] + lds[3 * K + k];
+    for (int k = 0; k < K; ++k) v[k] = (lds[k] + lds[K + k]) + (lds[2 * K + k] + lds[3 * K + k]);
     __syncthreads();
 }
 
@@ -67,21 +106,37 @@ __device__ __forceinline__ void lse_merge(double& m1, double& s1, double m2, dou
     else s1 = s1 + s2 * exp(m2 - m1);
 }
 
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ void lse_step(double& m, double& s) {
+    const double m2 = dpp_d<CTRL, ROW_MASK>(m, -INFINITY), s2 = dpp_d<CTRL, ROW_MASK>(s, 0.0);
+    lse_merge(m, s, m2, s2);
+}
+
+// log-sum-exp pair over the block; the result is returned to every thread
 __device__ void block_lse(double& m, double& s, double* lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
-        // combine symmetric pairs in a fixed order (lower lane first)
-        if ((lane & o) == 0) lse_merge(m, s, m2, s2);
-        else { double mm = m2, ss = s2; lse_merge(mm, ss, m, s); m = mm; s = ss; }
-    }
+    lse_step<kQuadX1>(m, s);
+    lse_step<kQuadX2>(m, s);
+    lse_step<kHalfMirror>(m, s);
+    lse_step<kMirror>(m, s);
+    lse_step<kBcast15, 0xA>(m, s);
+    lse_step<kBcast31, 0xC>(m, s);
+    m = readlane_d(m, 63);
+    s = readlane_d(s, 63);
     if (lane == 0) { lds[2 * wave] = m; lds[2 * wave + 1] = s; }
     __syncthreads();
     m = lds[0];
     s = lds[1];
     for (int w = 1; w < 4; ++w) lse_merge(m, s, lds[2 * w], lds[2 * w + 1]);
     __syncthreads();
+}
+
+// two-slot state by parity with constant indices (lets a copy of the control block
+// live in registers)
+__device__ __forceinline__ double pick2(const double (&a)[2], int k) { return k ? a[1] : a[0]; }
+__device__ __forceinline__ void put2(double (&a)[2], int k, double v) {
+    if (k) a[1] = v;
+    else a[0] = v;
 }
 
 // Cross-workgroup data inside one launch (tile partials, the points a strip's
@@ -208,9 +263,14 @@ struct Cand {
     double q0, q1, q2, q3, q4;
 };
 
+// select by value (a conditional on two members would select their addresses
+// and keep the struct in scratch memory)
+__device__ __forceinline__ double sel(int p, double a, double b) { return p ? a : b; }
+
+template <int PH>
 __device__ __forceinline__ Cand load_cand(const PassArgs& A, const SideVecs& V, int side, int i) {
     Cand q = {0.0, 0.0, 0.0, 0.0, 0.0};
-    switch (A.phase) {
+    switch (PH) {
     case PH_INIT: q.q0 = V.init ? V.init[i] : 0.0; break;
     case PH_BAR: q.q0 = V.chk0[i]; q.q1 = V.z[i]; q.q2 = V.d[i]; q.q3 = V.til0[i]; q.q4 = V.til1[i]; break;
     case PH_GRAVE: q.q0 = V.bar[i]; q.q1 = V.til0[i]; q.q2 = V.til1[i]; q.q3 = V.d[i]; break;
@@ -225,10 +285,11 @@ __device__ __forceinline__ Cand load_cand(const PassArgs& A, const SideVecs& V, 
     return q;
 }
 
-__device__ double eval_point(const PassArgs& A, const Ctl& c, const SideVecs& V, const Cand& q, int side,
-                             int i, bool writer) {
+template <int PH>
+__device__ __forceinline__ double eval_point(const PassArgs& A, const Ctl& c, const SideVecs& V, const Cand& q,
+                                           int side, int i, bool writer) {
     const int par = c.t & 1;
-    switch (A.phase) {
+    switch (PH) {
     case PH_INIT:
         if (writer) { V.chk0[i] = q.q0; V.til0[i] = q.q0; }
         return q.q0;
@@ -239,14 +300,14 @@ __device__ double eval_point(const PassArgs& A, const Ctl& c, const SideVecs& V,
             xc = q.q1 + (c.bchk == side ? q.q2 : 0.0);
             if (writer) (par ? V.chk1 : V.chk0)[i] = xc;
         }
-        const double xt = par ? q.q4 : q.q3;
+        const double xt = sel(par, q.q4, q.q3);
         const double xb = (1.0 - c.theta) * xc + c.theta * xt;    // zbar^t
         if (writer) V.bar[i] = xb;
         return xb;
     }
     case PH_GRAVE: {
         // z~^{t+1} = base - eta grad phi(zbar); z-grave = zbar + theta (z~^{t+1} - z~^t)
-        const double xb = q.q0, xt = par ? q.q2 : q.q1, g = q.q3;
+        const double xb = q.q0, xt = sel(par, q.q2, q.q1), g = q.q3;
         const double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
         const double xt1 = (A.step_rule == 0 ? xb : xt) - eta * g;
         const double xg = xb + c.theta * (xt1 - xt);
@@ -256,22 +317,23 @@ __device__ double eval_point(const PassArgs& A, const Ctl& c, const SideVecs& V,
     case PH_Z: {
         // z-hat^t = GreenkhornStep(z-grave^t); z^t = argmin phi over {z-check^t, z-hat^t}
         const double xh = q.q0 + (c.bhat == side ? q.q1 : 0.0);
-        const double z = c.pick ? xh : (par ? q.q3 : q.q2);
+        const double z = c.pick ? xh : sel(par, q.q3, q.q2);
         if (writer) V.z[i] = z;
         return z;
     }
-    case PH_SK_ROW: return side == 0 ? (par ? q.q1 : q.q0) : q.q0;   // a^k, b^k
-    case PH_SK_COL: return side == 0 ? (par ? q.q0 : q.q1) : q.q0;   // a^{k+1}, b^k
+    case PH_SK_ROW: return side == 0 ? sel(par, q.q1, q.q0) : q.q0;   // a^k, b^k
+    case PH_SK_COL: return side == 0 ? sel(par, q.q0, q.q1) : q.q0;   // a^{k+1}, b^k
     default: return 0.0;
     }
 }
 
 // scalar w of the point of each ASPOT pass
-__device__ double w_point(const PassArgs& A, const Ctl& c) {
+template <int PH>
+__device__ __forceinline__ double w_point(const PassArgs& A, const Ctl& c) {
     const int par = c.t & 1;
-    switch (A.phase) {
+    switch (PH) {
     case PH_INIT: return A.w0;
-    case PH_BAR: return (1.0 - c.theta) * c.wchk[par] + c.theta * c.wtil[par];
+    case PH_BAR: return (1.0 - c.theta) * pick2(c.wchk, par) + c.theta * pick2(c.wtil, par);
     case PH_GRAVE: return c.wgrave;
     case PH_Z: return c.wz;
     default: return 0.0;
@@ -279,68 +341,59 @@ __device__ double w_point(const PassArgs& A, const Ctl& c) {
 }
 
 // ---------------------------------------------------------------------------
-// per-row and per-column steps of the strip finalisers.
+// per-row and per-column steps of the finalising pass.  The state a step
+// reads is loaded (`load_step`) before the control block, together with the
+// tile partials, so that the pass makes a single round trip to memory.
 // acc slots: 0 T-part, 1 sum e^u, 2 <u, r~>, 3 <du, r~>, 4 rho score,
 //            5 E part, 6 spare, 7 non-finite count
 // ---------------------------------------------------------------------------
-__device__ void row_step(const PassArgs& A, const Ctl& c, int i, double R, double* acc) {
+struct StepPre {
+    double x0, x1, x2, x3;
+};
+
+template <int PH>
+__device__ __forceinline__ StepPre load_step(const PassArgs& A, bool row, int i) {
     const Ws& w = A.ws;
-    switch (A.phase) {
-    case PH_INIT: {
-        double u = w.uchk0[i];
-        acc[0] += R; acc[1] += exp(u); acc[2] += w.rt[i] * u;
-        acc[7] += isfinite(R) ? 0.0 : 1.0;
-        break;
-    }
-    case PH_BAR: {
-        // gradient of phi at zbar (Section 2.1): R + e^u - r~
-        double u = w.ubar[i];
-        w.du[i] = R + exp(u) - w.rt[i];
-        acc[0] += R;
-        acc[7] += isfinite(R) ? 0.0 : 1.0;
-        break;
-    }
-    case PH_GRAVE:
-    case PH_Z: {
-        double u = (A.phase == PH_GRAVE ? w.ugrave[i] : w.uz[i]);
-        double eu = exp(u), b = R + eu, lb = log(b);
-        double d = w.lrt[i] - lb;     // Greenkhorn u-step: u + log r~ - log(B1 + e^u)
-        w.du[i] = d;
-        acc[0] += R; acc[1] += eu; acc[2] += w.rt[i] * u; acc[3] += w.rt[i] * d;
-        acc[4] += rho_log(w.rt[i], w.lrt[i], lb);
-        acc[5] += fabs(b - w.rt[i]);
-        acc[7] += isfinite(R) ? 0.0 : 1.0;
-        break;
-    }
+    StepPre p = {0.0, 0.0, 0.0, 0.0};
+    const double* tv = row ? w.rt : w.ct;          // r~ or c~
+    const double* lv = row ? w.lrt : w.lct;        // their logs
+    switch (PH) {
+    case PH_INIT: p.x0 = (row ? w.uchk0 : w.vchk0)[i]; p.x1 = tv[i]; break;
+    case PH_BAR: p.x0 = (row ? w.ubar : w.vbar)[i]; p.x1 = tv[i]; break;
+    case PH_GRAVE: p.x0 = (row ? w.ugrave : w.vgrave)[i]; p.x1 = tv[i]; p.x2 = lv[i]; break;
+    case PH_Z: p.x0 = (row ? w.uz : w.vz)[i]; p.x1 = tv[i]; p.x2 = lv[i]; break;
+    case PH_SK_ROW: p.x0 = w.uchk0[i]; p.x1 = w.uchk1[i]; p.x2 = w.rt[i]; p.x3 = w.lrt[i]; break;
+    case PH_SK_COL: p.x0 = w.vz[i]; p.x1 = w.lct[i]; break;
     default: break;
     }
+    return p;
 }
 
-__device__ void col_step(const PassArgs& A, const Ctl& c, int j, double Q, double* acc) {
+// ASPOT step of row i (row) or column i: R is the row (column) sum of B at
+// the point of the pass, x0 the dual there, x1 the smoothed mass, x2 its log.
+template <int PH>
+__device__ __forceinline__ void aspot_step(const PassArgs& A, bool row, int i, double R, const StepPre& p,
+                                           double* acc) {
     const Ws& w = A.ws;
-    switch (A.phase) {
-    case PH_INIT: {
-        double v = w.vchk0[j];
-        acc[1] += exp(v); acc[2] += w.ct[j] * v;
-        acc[7] += isfinite(Q) ? 0.0 : 1.0;
+    const double x = p.x0, t = p.x1;
+    acc[7] += isfinite(R) ? 0.0 : 1.0;
+    if (row) acc[0] += R;
+    switch (PH) {
+    case PH_INIT:
+        acc[1] += exp(x); acc[2] += t * x;
         break;
-    }
-    case PH_BAR: {
-        double v = w.vbar[j];
-        w.dv[j] = Q + exp(v) - w.ct[j];
-        acc[7] += isfinite(Q) ? 0.0 : 1.0;
+    case PH_BAR:
+        // gradient of phi at zbar (Section 2.1): R + e^u - r~
+        (row ? w.du : w.dv)[i] = R + exp(x) - t;
         break;
-    }
     case PH_GRAVE:
     case PH_Z: {
-        double v = (A.phase == PH_GRAVE ? w.vgrave[j] : w.vz[j]);
-        double ev = exp(v), b = Q + ev, lb = log(b);
-        double d = w.lct[j] - lb;
-        w.dv[j] = d;
-        acc[1] += ev; acc[2] += w.ct[j] * v; acc[3] += w.ct[j] * d;
-        acc[4] += rho_log(w.ct[j], w.lct[j], lb);
-        acc[5] += fabs(b - w.ct[j]);
-        acc[7] += isfinite(Q) ? 0.0 : 1.0;
+        const double ex = exp(x), b = R + ex, lb = log(b);
+        const double d = p.x2 - lb;                 // Greenkhorn step: u + log r~ - log(B 1 + e^u)
+        (row ? w.du : w.dv)[i] = d;
+        acc[1] += ex; acc[2] += t * x; acc[3] += t * d;
+        acc[4] += rho_log(t, p.x2, lb);
+        acc[5] += fabs(b - t);
         break;
     }
     default: break;
@@ -386,38 +439,56 @@ __device__ double phi_after(const Ctl& c, int block, const double* R, const doub
     }
 }
 
-__device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
+__device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const double* Rs, const double* Cs);
+
+// The deciding block: gathers every block's sums (all threads), then thread 0
+// runs the iteration's scalar logic on the LDS snapshot of the control block
+// and the block writes the snapshot back.
+__device__ void decide(const PassArgs& A, Ctl& cs, double* lds) {
     double Rs[kScal], Cs[kScal];
     const bool rows = A.phase != PH_SK_COL;
     const bool cols = A.phase != PH_SK_ROW;
+    const bool sk = A.phase == PH_SK_ROW || A.phase == PH_SK_COL;
     {
-        // both gathers' loads in flight together, then one block reduction
+        // every block's sums in one batch of loads; Sinkhorn passes also merge
+        // the blocks' (max, sum of exp) pairs (one side only) in a fixed tree
+        const int nr = rows ? A.nrb : 0, nb = nr + (cols ? A.ncb : 0);
         double v[2 * kScal];
 #pragma unroll
         for (int k = 0; k < 2 * kScal; ++k) v[k] = 0.0;
-        if (rows)
-            for (int b = threadIdx.x; b < A.nrb; b += kThreads)
+        double mx = -INFINITY, se = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kThreads) {
+            const bool isr = b < nr;
+            const double* p = isr ? A.ws.rowscal + (int64_t)b * kScal : A.ws.colscal + (int64_t)(b - nr) * kScal;
+            double x[kScal];
 #pragma unroll
-                for (int k = 0; k < kScal; ++k) v[k] += ld_agent(&A.ws.rowscal[(int64_t)b * kScal + k]);
-        if (cols)
-            for (int b = threadIdx.x; b < A.ncb; b += kThreads)
+            for (int k = 0; k < kScal; ++k) x[k] = ld_agent(&p[k]);
 #pragma unroll
-                for (int k = 0; k < kScal; ++k) v[kScal + k] += ld_agent(&A.ws.colscal[(int64_t)b * kScal + k]);
+            for (int k = 0; k < kScal; ++k) {
+                v[k] += isr ? x[k] : 0.0;
+                v[kScal + k] += isr ? 0.0 : x[k];
+            }
+            if (sk) lse_merge(mx, se, x[1], x[2]);
+        }
         block_sum<2 * kScal>(v, lds);
+        if (sk) block_lse(mx, se, lds);
 #pragma unroll
         for (int k = 0; k < kScal; ++k) { Rs[k] = v[k]; Cs[k] = v[kScal + k]; }
+        if (sk) {
+            if (rows) { Rs[1] = mx; Rs[2] = se; }
+            else { Cs[1] = mx; Cs[2] = se; }
+        }
     }
-    if (threadIdx.x != 0) return;
-    if (A.phase == PH_SK_ROW || A.phase == PH_SK_COL) {
-        // slots 1, 2 hold per-strip (max, sum of exp): merge them in strip order
-        const double* part = rows ? A.ws.rowscal : A.ws.colscal;
-        const int ns = rows ? A.nrb : A.ncb;
-        double mx = -INFINITY, se = 0.0;
-        for (int k = 0; k < ns; ++k)
-            lse_merge(mx, se, ld_agent(&part[(int64_t)k * kScal + 1]), ld_agent(&part[(int64_t)k * kScal + 2]));
-        if (rows) { Rs[1] = mx; Rs[2] = se; }
-        else { Cs[1] = mx; Cs[2] = se; }
-    }
+    if (threadIdx.x == 0) decide_logic(A, cs, Rs, Cs);
+    __syncthreads();
+    constexpr int kCtlWords = sizeof(Ctl) / 8;
+    if (threadIdx.x < kCtlWords)
+        reinterpret_cast<uint64_t*>(A.ws.ctl)[threadIdx.x] = reinterpret_cast<const uint64_t*>(&cs)[threadIdx.x];
+}
+
+__device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const double* Rs, const double* Cs) {
+    const bool rows = A.phase != PH_SK_COL;
+    const bool cols = A.phase != PH_SK_ROW;
     const int t = c.t, par = t & 1;
     // a non-finite sum, or (ASPOT) a total that underflowed even the FP64
     // range after the tiles' shifts: the statistics cannot be represented
@@ -443,12 +514,12 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
     }
     case PH_BAR: {
         double gw = Rs[0] - c.s;                         // d phi / d w at zbar
-        double wb = (1.0 - c.theta) * c.wchk[par] + c.theta * c.wtil[par];
+        double wb = (1.0 - c.theta) * pick2(c.wchk, par) + c.theta * pick2(c.wtil, par);
         double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
-        double wt1 = (A.step_rule == 0 ? wb : c.wtil[par]) - eta * gw;
+        double wt1 = (A.step_rule == 0 ? wb : pick2(c.wtil, par)) - eta * gw;
         c.wbar = wb;
-        c.wtil[par ^ 1] = wt1;
-        c.wgrave = wb + c.theta * (wt1 - c.wtil[par]);
+        put2(c.wtil, par ^ 1, wt1);
+        c.wgrave = wb + c.theta * (wt1 - pick2(c.wtil, par));
         break;
     }
     case PH_GRAVE: {
@@ -463,7 +534,7 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
         c.bhat = b;
         c.pick = pick;
         c.phihat = ph;
-        c.wz = pick ? wh : c.wchk[par];
+        c.wz = pick ? wh : pick2(c.wchk, par);
         if (A.trace_i && t < A.trace_cap) {
             A.trace_i[3 * t + 0] = b;
             A.trace_i[3 * t + 1] = pick;
@@ -495,7 +566,7 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
         if (A.force && t < A.force_len) b = A.force[3 * t + 2];
         c.bchk = b;
         c.phichk = phi_after(c, b, Rs, Cs, c.wz);
-        c.wchk[par ^ 1] = c.wz + (b == 2 ? c.log_s - log(T) : 0.0);
+        put2(c.wchk, par ^ 1, c.wz + (b == 2 ? c.log_s - log(T) : 0.0));
         if (A.trace_i && t < A.trace_cap) A.trace_i[3 * t + 2] = b;
         c.theta = c.theta * (sqrt(c.theta * c.theta + 4.0) - c.theta) / 2.0;
         c.t = t + 1;
@@ -510,7 +581,7 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
     }
     case PH_SK_ROW: {
         // row error of iterate t-1 (columns are exact after the b update)
-        double ad = c.ad[par];
+        double ad = pick2(c.ad, par);
         double rs_d = exp(ad + c.lse_b) + exp(ad + c.bd - c.A / c.gamma);
         double E = Rs[0] + fabs(rs_d - c.rhat_d);
         bool stop = false;
@@ -527,12 +598,12 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
             c.out_par = par;
             break;
         }
-        c.ad[par ^ 1] = c.lrhat_d - logaddexp(c.lse_b, c.bd - c.A / c.gamma);
+        put2(c.ad, par ^ 1, c.lrhat_d - logaddexp(c.lse_b, c.bd - c.A / c.gamma));
         c.lse_a = Rs[1] + log(Rs[2]);
         break;
     }
     case PH_SK_COL: {
-        double adn = c.ad[par ^ 1];
+        double adn = pick2(c.ad, par ^ 1);
         c.bd = c.lchat_d - logaddexp(c.lse_a, adn - c.A / c.gamma);
         c.lse_b = Cs[1] + log(Cs[2]);
         c.t = t + 1;
@@ -542,23 +613,25 @@ __device__ void decide(const PassArgs& A, Ctl& c, double* lds) {
     }
 }
 
-// Sinkhorn strip finalisers need log-sum-exp partials; they are separate
-// because they take two reductions (max, then sum).
+// Sinkhorn steps of the finalising pass: one row (column) per thread of the
+// first wave; the block's outputs are {error, max, sum of exp, 0.., non-finite}.
 __device__ void sk_row_finalise(const PassArgs& A, const Ctl& c, int i0, int rows, const double* R,
-                                double* out, double* lds) {
+                                const StepPre& p, double* out, double* lds) {
     const Ws& w = A.ws;
     const int par = c.t & 1;
-    const double* a = par ? w.uchk1 : w.uchk0;
     double* an = par ? w.uchk0 : w.uchk1;
     double err = 0.0, nonf = 0.0, mx = -INFINITY, se = 0.0;
-    for (int r = threadIdx.x; r < rows; r += kThreads) {
-        int i = i0 + r;
-        double rs = R[r] + exp(a[i] + c.bd);          // dummy column: cost 0
-        err += fabs(rs - w.rt[i]);
-        nonf += (isfinite(R[r]) && rs > 0.0) ? 0.0 : 1.0;
-        double anew = a[i] + w.lrt[i] - log(rs);      // u <- u + log r^ - log(X^ 1)
+    const int r = threadIdx.x;
+    if (r < rows) {
+        const int i = i0 + r;
+        const double a = par ? p.x1 : p.x0;
+        const double rs = R[r] + exp(a + c.bd);        // dummy column: cost 0
+        err = fabs(rs - p.x2);
+        nonf = (isfinite(R[r]) && rs > 0.0) ? 0.0 : 1.0;
+        const double anew = a + p.x3 - log(rs);        // u <- u + log r^ - log(X^ 1)
         an[i] = anew;
-        lse_merge(mx, se, anew, 1.0);
+        mx = anew;
+        se = 1.0;
     }
     block_lse(mx, se, lds);
     double v[2] = {err, nonf};
@@ -571,18 +644,20 @@ __device__ void sk_row_finalise(const PassArgs& A, const Ctl& c, int i0, int row
 }
 
 __device__ void sk_col_finalise(const PassArgs& A, const Ctl& c, int j0, int cols, const double* Q,
-                                double* out, double* lds) {
+                                const StepPre& p, double* out, double* lds) {
     const Ws& w = A.ws;
     const int par = c.t & 1;
-    const double adn = c.ad[par ^ 1];
+    const double adn = pick2(c.ad, par ^ 1);
     double nonf = 0.0, mx = -INFINITY, se = 0.0;
-    for (int q = threadIdx.x; q < cols; q += kThreads) {
-        int j = j0 + q;
-        double cs = Q[q] + exp(adn + w.vz[j]);        // dummy row: cost 0
-        nonf += (isfinite(Q[q]) && cs > 0.0) ? 0.0 : 1.0;
-        double bnew = w.vz[j] + w.lct[j] - log(cs);
+    const int q = threadIdx.x;
+    if (q < cols) {
+        const int j = j0 + q;
+        const double cs = Q[q] + exp(adn + p.x0);       // dummy row: cost 0
+        nonf = (isfinite(Q[q]) && cs > 0.0) ? 0.0 : 1.0;
+        const double bnew = p.x0 + p.x1 - log(cs);
         w.vz[j] = bnew;
-        lse_merge(mx, se, bnew, 1.0);
+        mx = bnew;
+        se = 1.0;
     }
     block_lse(mx, se, lds);
     double v[1] = {nonf};
@@ -598,10 +673,13 @@ __device__ void sk_col_finalise(const PassArgs& A, const Ctl& c, int j0, int col
 // the statistics pass
 // ---------------------------------------------------------------------------
 constexpr int kMaxBR = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));   // 16-byte vector of the tile loads
 constexpr int kMaxBC = 512;
 
-template <int KIND, bool ROWS, bool COLS>
+template <int KIND, int PHASE>
 __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
+    constexpr bool ROWS = PHASE != PH_SK_COL;     // the pass needs row sums
+    constexpr bool COLS = PHASE != PH_SK_ROW;     // ... column sums
     constexpr int VW = (KIND == POT_COST_BF16) ? 8 : 4;
     constexpr bool PTS = (KIND == POT_COST_SQEUCLID_POINTS);
     constexpr int EB = (KIND == POT_COST_BF16) ? 2 : 4;      // bytes per stored cost
@@ -625,26 +703,30 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     const int rows = min(A.br, A.n - i0), cols = min(A.bc, A.m - j0);
     const int jg = j0 + lane * VW;         // this lane's first column
 
-    // ---- interior tiles: the first batch of costs is loaded while the
-    // prologue computes the point of the pass (a converged solve exits
-    // below; the hardware drains outstanding loads at the end of a wave)
+    // ---- loads, in the order they are needed (vector loads complete in
+    // order): the candidate state of this thread's row (tid) and columns
+    // (tid, tid + 256) and the tile's shift, then the first batch of costs,
+    // which stays in flight while the prologue computes the point of the pass
+    // (a converged solve exits below; the hardware drains outstanding loads
+    // at the end of a wave)
+    // (indices are clamped into range so that the loads are not divergent:
+    // a divergent load ends in a wait for every load before it)
+    constexpr int NCC = (64 * VW + kThreads - 1) / kThreads;    // column candidates per thread
+    const SideVecs RV = side_vecs(A, 0), CV = side_vecs(A, 1);
+    const Cand rq = load_cand<PHASE>(A, RV, 0, i0 + min(tid, rows - 1));
+    Cand cq[NCC];
+#pragma unroll
+    for (int h = 0; h < NCC; ++h) cq[h] = load_cand<PHASE>(A, CV, 1, j0 + min(tid + h * kThreads, cols - 1));
+    int K = A.ws.tshift[tile];             // this tile's shift, kept from its previous pass
     const bool vec_ok = !PTS && ((A.ldc % VW) == 0) && ((((uintptr_t)A.C) & 15) == 0);
     const bool fast = (PTS || vec_ok) && rows == A.br && (A.br % 64) == 0 && j0 + A.bc <= A.m;
     const char* cbase = (const char*)A.C + ((int64_t)(i0 + wave) * A.ldc + jg) * EB;   // row i0 + wave
     const int64_t rstep = (int64_t)4 * A.ldc * EB;                                      // 4 rows down
-    float4 pre[U];
+    f32x4 pre[U];
     if (!PTS && fast) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) pre[u] = *(const float4*)(cbase + u * rstep);
+        for (int u = 0; u < U; ++u) pre[u] = *(const f32x4*)(cbase + u * rstep);
     }
-    // candidate state of this thread's row (tid) and columns (tid, tid + 256)
-    const SideVecs RV = side_vecs(A, 0), CV = side_vecs(A, 1);
-    Cand rq = {0.0, 0.0, 0.0, 0.0, 0.0}, cq[2] = {rq, rq};
-    if (tid < rows) rq = load_cand(A, RV, 0, i0 + tid);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-        if (tid + h * kThreads < cols) cq[h] = load_cand(A, CV, 1, j0 + tid + h * kThreads);
-    int K = A.ws.tshift[tile];             // this tile's shift, kept from its previous pass
 
     Ctl& c = *A.ws.ctl;
     if (c.done) return;                     // converged earlier: nothing to do
@@ -653,14 +735,14 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     // in log2 units; the duals are clamped to +-2^29 so that every exponent
     // below fits the split of exp2_split (|G * C| < 2^29 is checked on the host)
     const double G = c.G;
-    const double wp = w_point(A, c);
+    const double wp = w_point<PHASE>(A, c);
     constexpr double kClamp = 536870912.0;  // 2^29
     double ox[3] = {0.0, 0.0, 0.0};        // points: tile origin (first source point)
     if (PTS) {
         for (int k = 0; k < A.d; ++k) ox[k] = (double)A.x[(int64_t)i0 * A.d + k];
     }
     if (tid < rows) {
-        double a = fmin(fmax((eval_point(A, c, RV, rq, 0, i0 + tid, tx == 0) + wp) * kLog2e, -kClamp), kClamp);
+        double a = fmin(fmax((eval_point<PHASE>(A, c, RV, rq, 0, i0 + tid, tx == 0) + wp) * kLog2e, -kClamp), kClamp);
         if (PTS) {
             // t_ij = a_i + b_j - G |x_i - y_j|^2, with x, y taken relative to the
             // origin o: (a_i - G|x_i - o|^2) + (b_j - G|y_j - o|^2) + 2G (x_i - o).(y_j - o)
@@ -675,11 +757,11 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         s_a[tid] = a - (double)K;
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NCC; ++h) {
         const int q = tid + h * kThreads;
         if (q < cols) {
             const int j = j0 + q;
-            double v = fmin(fmax(eval_point(A, c, CV, cq[h], 1, j, ty == 0) * kLog2e, -kClamp), kClamp);
+            double v = fmin(fmax(eval_point<PHASE>(A, c, CV, cq[h], 1, j, ty == 0) * kLog2e, -kClamp), kClamp);
             if (PTS) {
                 double yy = 0.0;
                 for (int k = 0; k < 3; ++k) {
@@ -720,7 +802,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     double colacc[VW];
 
     // terms of one row: returns the row's lane partial and adds to col32
-    auto row_terms = [&](auto full_tag, const float* cv, int r, double a, float* col32) -> float {
+    auto row_terms = [&](auto full_tag, const float* cv, int r, double a, float* col32) __attribute__((always_inline)) -> float {
         constexpr bool FULL = decltype(full_tag)::value;
         float e[VW];
         if constexpr (PTS) {
@@ -751,15 +833,15 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     };
 
     // reduce the per-lane row partials of a 64-row chunk; write them; level
-    auto emit_rows = [&](int c0, double scale_d, double& lvl) {
+    auto emit_rows = [&](int c0, double scale_d, double& lvl) __attribute__((always_inline)) {
         __syncthreads();
         const int rl = tid >> 2, q = tid & 3;          // row of the chunk, quarter of the lanes
         const int wv = rl & 3, slot = rl >> 2;         // row rl = wave wv's slot-th row
         double sacc = 0.0;
 #pragma unroll
         for (int l = 0; l < 16; ++l) sacc += (double)s_rowp[wv][slot][q * 16 + l];
-        sacc += __shfl_xor(sacc, 1, 64);
-        sacc += __shfl_xor(sacc, 2, 64);
+        sacc += dpp_d<kQuadX1>(sacc, 0.0);
+        sacc += dpp_d<kQuadX2>(sacc, 0.0);
         const int r = c0 + rl;
         if (r < rows) {
             lvl = fmax(lvl, sacc);                     // (NaN sums reach the finalisers' check)
@@ -768,21 +850,21 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         __syncthreads();
     };
 
-    auto sweep = [&](bool use_pre, double scale_d) -> double {
+    auto sweep = [&](bool use_pre, double scale_d) __attribute__((always_inline)) -> double {
         double lvl = 0.0;
 #pragma unroll
         for (int k = 0; k < VW; ++k) colacc[k] = 0.0;
         for (int c0 = 0; c0 < rows; c0 += 64) {
             // this wave's rows of the chunk: c0 + wave + 4 * slot, slot = 0..15
             if (fast) {
-                float4 cur[U], nxt[U];
+                f32x4 cur[U], nxt[U];
                 if (!PTS) {
                     if (use_pre && c0 == 0) {
 #pragma unroll
                         for (int u = 0; u < U; ++u) cur[u] = pre[u];
                     } else {
 #pragma unroll
-                        for (int u = 0; u < U; ++u) cur[u] = *(const float4*)(cbase + ((int64_t)c0 / 4 + u) * rstep);
+                        for (int u = 0; u < U; ++u) cur[u] = *(const f32x4*)(cbase + ((int64_t)c0 / 4 + u) * rstep);
                     }
                 }
 #pragma unroll
@@ -790,7 +872,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
                     if (!PTS && bb + 1 < 16 / U) {
 #pragma unroll
                         for (int u = 0; u < U; ++u)
-                            nxt[u] = *(const float4*)(cbase + ((int64_t)c0 / 4 + (bb + 1) * U + u) * rstep);
+                            nxt[u] = *(const f32x4*)(cbase + ((int64_t)c0 / 4 + (bb + 1) * U + u) * rstep);
                     }
                     double av[U];
 #pragma unroll
@@ -803,15 +885,15 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
                         const int slot = bb * U + u, r = c0 + wave + 4 * slot;
                         float cv[VW];
                         if constexpr (KIND == POT_COST_BF16) {
-                            const uint32_t w4[4] = {__float_as_uint(cur[u].x), __float_as_uint(cur[u].y),
-                                                    __float_as_uint(cur[u].z), __float_as_uint(cur[u].w)};
+                            const uint32_t w4[4] = {__float_as_uint(cur[u][0]), __float_as_uint(cur[u][1]),
+                                                    __float_as_uint(cur[u][2]), __float_as_uint(cur[u][3])};
 #pragma unroll
                             for (int k = 0; k < 4; ++k) {
                                 cv[2 * k] = __uint_as_float(w4[k] << 16);
                                 cv[2 * k + 1] = __uint_as_float(w4[k] & 0xffff0000u);
                             }
                         } else if constexpr (KIND == POT_COST_F32) {
-                            cv[0] = cur[u].x; cv[1] = cur[u].y; cv[2] = cur[u].z; cv[3] = cur[u].w;
+                            cv[0] = cur[u][0]; cv[1] = cur[u][1]; cv[2] = cur[u][2]; cv[3] = cur[u][3];
                         }
                         s_rowp[wave][slot][lane] =
                             row_terms(std::integral_constant<bool, true>{}, cv, r, av[u], col32);
@@ -873,8 +955,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     };
 
     auto block_level = [&](double v) -> double {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        v = wave_max(v);
         if (lane == 0) s_lvl[wave] = v;
         __syncthreads();
         double l = fmax(fmax(s_lvl[0], s_lvl[1]), fmax(s_lvl[2], s_lvl[3]));
@@ -892,8 +973,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         else {
             // every sum flushed to 0 or overflowed: locate the largest term
             double mx = max_exponent();
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+            mx = wave_max(mx);
             if (lane == 0) s_lvl[wave] = mx;
             __syncthreads();
             mx = fmax(fmax(s_lvl[0], s_lvl[1]), fmax(s_lvl[2], s_lvl[3]));
@@ -932,66 +1012,73 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
 // ---------------------------------------------------------------------------
 constexpr int kFinBlock = 64;
 
+template <int PHASE>
 __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
     __shared__ double s_part[4][kFinBlock];
     __shared__ double s_v[kFinBlock];
-    __shared__ double s_red[64];
+    __shared__ double s_red[4 * 2 * kScal];
     __shared__ int s_last;
-    Ctl& c = *A.ws.ctl;
-    if (c.done) return;
+    __shared__ Ctl s_ctl;                              // snapshot of the control block
+    static_assert(sizeof(Ctl) % 8 == 0 && sizeof(Ctl) / 8 <= kThreads, "control block copy");
+    constexpr int kCtlWords = sizeof(Ctl) / 8;
     const int tid = threadIdx.x;
-    const bool rows_pass = A.phase != PH_SK_COL;
+    constexpr bool rows_pass = PHASE != PH_SK_COL;
     const int blk = blockIdx.x;
     const bool is_row = rows_pass && blk < A.nrb;
     const int cb = rows_pass ? blk - A.nrb : blk;      // column block index
     const int base = is_row ? blk * kFinBlock : cb * kFinBlock;
     const int len = min(kFinBlock, (is_row ? A.n : A.m) - base);
-    // sum of the tile partials: 4 threads per row (column), each a quarter of
-    // the strips, combined in a fixed order
+    // loads first, all in one batch: the control block, the tile partials (4
+    // threads per row or column, each a quarter of the strips) and the state
+    // of the step
+    const uint64_t cw = tid < kCtlWords ? reinterpret_cast<const uint64_t*>(A.ws.ctl)[tid] : 0;
+    // (indices clamped into range: no divergent loads)
+    const int l = tid & (kFinBlock - 1), q = tid / kFinBlock;
+    double acc = 0.0;
     {
-        const int l = tid & (kFinBlock - 1), q = tid / kFinBlock;
-        double acc = 0.0;
-        if (l < len) {
-            if (is_row) {
-                const double* p = (const double*)A.ws.rowpart + base + l;
+        const int lc = min(l, len - 1);
+        if (is_row) {
+            const double* p = (const double*)A.ws.rowpart + base + lc;
 #pragma unroll 4
-                for (int x = q; x < A.nx; x += 4) acc += p[(int64_t)x * A.n];
-            } else {
-                const double* p = (const double*)A.ws.colpart + base + l;
+            for (int x = q; x < A.nx; x += 4) acc += p[(int64_t)x * A.n];
+        } else {
+            const double* p = (const double*)A.ws.colpart + base + lc;
 #pragma unroll 4
-                for (int y = q; y < A.ny; y += 4) acc += p[(int64_t)y * A.m];
-            }
+            for (int y = q; y < A.ny; y += 4) acc += p[(int64_t)y * A.m];
         }
-        s_part[q][l] = acc;
-        __syncthreads();
-        if (tid < kFinBlock) s_v[tid] = (s_part[0][tid] + s_part[1][tid]) + (s_part[2][tid] + s_part[3][tid]);
-        __syncthreads();
+        if (l >= len) acc = 0.0;
     }
+    const StepPre pre = load_step<PHASE>(A, is_row, base + min(tid, len - 1));
+    if (tid < kCtlWords) reinterpret_cast<uint64_t*>(&s_ctl)[tid] = cw;
+    s_part[q][l] = acc;
+    __syncthreads();
+    const Ctl& c = s_ctl;
+    if (c.done) return;              // (uniform: every thread reads the same word)
+    // the partials combined in a fixed order
+    if (tid < kFinBlock) s_v[tid] = (s_part[0][tid] + s_part[1][tid]) + (s_part[2][tid] + s_part[3][tid]);
+    __syncthreads();
     double* out = (is_row ? A.ws.rowscal + (int64_t)blk * kScal : A.ws.colscal + (int64_t)cb * kScal);
-    if (A.phase == PH_SK_ROW) {
-        sk_row_finalise(A, c, base, len, s_v, out, s_red);
-    } else if (A.phase == PH_SK_COL) {
-        sk_col_finalise(A, c, base, len, s_v, out, s_red);
+    if constexpr (PHASE == PH_SK_ROW) {
+        sk_row_finalise(A, c, base, len, s_v, pre, out, s_red);
+    } else if constexpr (PHASE == PH_SK_COL) {
+        sk_col_finalise(A, c, base, len, s_v, pre, out, s_red);
     } else {
-        double acc[kScal];
+        double sums[kScal];
 #pragma unroll
-        for (int k = 0; k < kScal; ++k) acc[k] = 0.0;
-        if (tid < len) {
-            if (is_row) row_step(A, c, base + tid, s_v[tid], acc);
-            else col_step(A, c, base + tid, s_v[tid], acc);
-        }
-        block_sum<kScal>(acc, s_red);
+        for (int k = 0; k < kScal; ++k) sums[k] = 0.0;
+        if (tid < len) aspot_step<PHASE>(A, is_row, base + tid, s_v[tid], pre, sums);
+        block_sum<kScal>(sums, s_red);
         if (tid == 0)
-            for (int k = 0; k < kScal; ++k) st_agent(&out[k], acc[k]);
+            for (int k = 0; k < kScal; ++k) st_agent(&out[k], sums[k]);
     }
     // arrival: the last block decides
     wait_stores();
     __syncthreads();
-    const int total = (rows_pass ? A.nrb : 0) + (A.phase != PH_SK_ROW ? A.ncb : 0);
+    const int total = (rows_pass ? A.nrb : 0) + (PHASE != PH_SK_ROW ? A.ncb : 0);
     if (tid == 0) s_last = (atomicAdd(&A.ws.glob[0], 1) == total - 1);
     __syncthreads();
     if (s_last) {
-        decide(A, c, s_red);
+        decide(A, s_ctl, s_red);
         if (tid == 0) A.ws.glob[0] = 0;
     }
 }
@@ -1402,26 +1489,32 @@ static int fin_blocks(const PassArgs& A) {
     return (A.phase != PH_SK_COL ? A.nrb : 0) + (A.phase != PH_SK_ROW ? A.ncb : 0);
 }
 
-template <int KIND, bool ROWS, bool COLS>
+template <int KIND, int PHASE>
 static hipError_t launch_stats_k(const PassArgs& A, hipStream_t st) {
-    stats_pass<KIND, ROWS, COLS><<<A.nx * A.ny, kThreads, 0, st>>>(A);
-    fin_pass<<<fin_blocks(A), kThreads, 0, st>>>(A);
+    stats_pass<KIND, PHASE><<<A.nx * A.ny, kThreads, 0, st>>>(A);
+    fin_pass<PHASE><<<fin_blocks(A), kThreads, 0, st>>>(A);
     return hipGetLastError();
 }
 
-template <bool ROWS, bool COLS>
-static hipError_t launch_stats_kind(const PassArgs& A, hipStream_t st) {
-    switch (A.kind) {
-    case POT_COST_F32: return launch_stats_k<POT_COST_F32, ROWS, COLS>(A, st);
-    case POT_COST_BF16: return launch_stats_k<POT_COST_BF16, ROWS, COLS>(A, st);
-    default: return launch_stats_k<POT_COST_SQEUCLID_POINTS, ROWS, COLS>(A, st);
+template <int KIND>
+static hipError_t launch_stats_phase(const PassArgs& A, hipStream_t st) {
+    switch (A.phase) {
+    case PH_INIT: return launch_stats_k<KIND, PH_INIT>(A, st);
+    case PH_BAR: return launch_stats_k<KIND, PH_BAR>(A, st);
+    case PH_GRAVE: return launch_stats_k<KIND, PH_GRAVE>(A, st);
+    case PH_Z: return launch_stats_k<KIND, PH_Z>(A, st);
+    case PH_SK_ROW: return launch_stats_k<KIND, PH_SK_ROW>(A, st);
+    case PH_SK_COL: return launch_stats_k<KIND, PH_SK_COL>(A, st);
+    default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_stats(const PassArgs& A, hipStream_t st) {
-    if (A.phase == PH_SK_ROW) return launch_stats_kind<true, false>(A, st);
-    if (A.phase == PH_SK_COL) return launch_stats_kind<false, true>(A, st);
-    return launch_stats_kind<true, true>(A, st);
+    switch (A.kind) {
+    case POT_COST_F32: return launch_stats_phase<POT_COST_F32>(A, st);
+    case POT_COST_BF16: return launch_stats_phase<POT_COST_BF16>(A, st);
+    default: return launch_stats_phase<POT_COST_SQEUCLID_POINTS>(A, st);
+    }
 }
 
 // Timed launch of the statistics pass: start/stop events recorded around the
@@ -1429,8 +1522,8 @@ hipError_t launch_stats(const PassArgs& A, hipStream_t st) {
 template <int KIND>
 static hipError_t launch_stats_timed_k(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
                                        hipEvent_t e2, hipEvent_t e3) {
-    hipExtLaunchKernelGGL((stats_pass<KIND, true, true>), dim3(A.nx * A.ny), dim3(kThreads), 0, st, e0, e1, 0, A);
-    hipExtLaunchKernelGGL(fin_pass, dim3(fin_blocks(A)), dim3(kThreads), 0, st, e2, e3, 0, A);
+    hipExtLaunchKernelGGL((stats_pass<KIND, PH_INIT>), dim3(A.nx * A.ny), dim3(kThreads), 0, st, e0, e1, 0, A);
+    hipExtLaunchKernelGGL(fin_pass<PH_INIT>, dim3(fin_blocks(A)), dim3(kThreads), 0, st, e2, e3, 0, A);
     return hipGetLastError();
 }
 
