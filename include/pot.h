@@ -110,7 +110,10 @@ typedef struct {
     int32_t* trace_i;      /* (device) per-iteration decisions, 3 ints each, or NULL */
     double* trace_d;       /* (device) per-iteration values {E, phi(z-check^t), phi(z-hat^t), theta_t}, or NULL */
     int32_t trace_cap;     /* iterations the trace buffers hold */
-    int32_t tile_rows;     /* rows per tile of the statistics pass (0: autotuned) */
+    int32_t tile_rows;     /* rows per tile of the statistics pass (0: chosen from the grid size) */
+    int32_t member_elems;  /* pot_solve_batched: an instance with more than this many cost entries is
+                              split by rows over a group of workgroups, each sweeping at most this
+                              many (0: autotuned on the batch, cached per batch shape) */
 } pot_options;
 
 typedef struct {
@@ -150,18 +153,36 @@ size_t pot_workspace_bytes(const pot_problem* prob, const pot_options* opts);
 pot_status pot_solve(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
                      pot_result* res, const pot_outputs* out, void* stream);
 
+/* Warm starts of a batch (pot_solve_batched). */
+typedef struct {
+    const double* const* u0;   /* host array of `batch` device pointers to u0 (n_k each), entries may be NULL */
+    const double* const* v0;   /* host array of device pointers to v0 (m_k each), entries may be NULL */
+    const double* w0;          /* host array of `batch` values of w0, or NULL (all 0) */
+    int32_t check;             /* 1: keep an instance's warm start only if phi(z0) < phi(0), else start
+                                  it cold (one or two more statistics passes per instance) */
+} pot_warm;
+
 /* Workspace for pot_solve_batched over these problems. */
 size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, const pot_options* opts);
 
-/* Solve `batch` independent instances (dense F32/BF16 or points costs, up to
- * 4096 points per side) in one persistent launch: one workgroup per instance
- * at a time, instances taken from a device queue largest first.  probs (host
- * array) describe each instance with device pointers; opts apply to all;
- * res (host array of batch) receives per-instance results; f_out/g_out
- * (host arrays of device pointers, may be NULL) receive the log scalings.
- * Returns POT_OK if every instance is OK, else the first failing status. */
+/* Solve `batch` independent instances in one persistent launch (a captured
+ * HIP graph of two kernels unless POT_FLAG_NO_GRAPH).  Each instance is a
+ * dense POT_COST_F32 or POT_COST_BF16 cost (the same kind for the whole
+ * batch) with 1 <= n, m <= 1024; the algorithm, its defaults and the
+ * rounding are those of pot_solve, per instance.  Workgroups take instances
+ * from a device queue, largest first; an instance with more than
+ * opts->member_elems cost entries is split by rows over a group of up to 8
+ * workgroups.  probs (host array) describe the instances with device
+ * pointers (cmax <= 0: scanned on the device); opts apply to all (force and
+ * trace must be NULL; tile_rows is ignored); warm (may be NULL) gives
+ * per-instance warm starts; res (host array of batch) receives the results
+ * (used_warm reports whether the warm start was kept); f_out / g_out (host
+ * arrays of device pointers, may be NULL, entries may be NULL) receive the
+ * log scalings of X~.  Returns POT_OK if every instance is OK, else the
+ * first failing status; POT_ERR_DEVICE for an instance whose group of
+ * workgroups could not meet (a bounded wait expired). */
 pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_options* opts,
-                             void* ws, size_t ws_bytes, pot_result* res,
+                             const pot_warm* warm, void* ws, size_t ws_bytes, pot_result* res,
                              double* const* f_out, double* const* g_out, void* stream);
 
 /* Measurement hook: set up the problem (as pot_solve does) and run the

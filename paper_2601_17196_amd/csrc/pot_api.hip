@@ -6,7 +6,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pot_internal.h"
@@ -25,6 +28,8 @@ hipError_t launch_copy_out(const PassArgs& A, double* alpha, double* beta, doubl
 
 hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
                               hipEvent_t e3);
+int batched_blocks_per_cu(int kind);
+hipError_t launch_batched(const BArgs& B, int kind, int grid, hipStream_t st);
 
 static thread_local std::string g_last_error;
 
@@ -47,9 +52,14 @@ static Geometry geometry(const pot_problem* p, const pot_options* o) {
     g.bc = 64 * vec_width(p->kind);
     int br = (o && o->tile_rows > 0) ? o->tile_rows : 0;
     if (br == 0) {
-        // default: rows per tile so that the grid has a few WGs per CU
-        const int64_t elems = (int64_t)p->n * p->m;
-        br = elems >= (int64_t)8192 * 8192 ? 128 : 64;
+        // default: the tallest tile (fewer row partials, a longer sweep per
+        // workgroup) that still gives at least 2 workgroups per CU (512 on
+        // 256 CUs); measured best on 4096 x 4096 for FP32 (128 rows) and
+        // BF16 (64 rows)
+        const int nx = (p->m + g.bc - 1) / g.bc;
+        br = 64;
+        for (int cand : {256, 128})
+            if ((int64_t)nx * ((p->n + cand - 1) / cand) >= 512) { br = cand; break; }
     }
     br = std::max(4, std::min(br, 256));
     g.br = br;
@@ -139,7 +149,7 @@ static thread_local PollSlots g_poll;
 
 static pot_status ensure_poll() {
     if (!g_poll.flag) {
-        HIPCHK(hipHostMalloc((void**)&g_poll.flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&g_poll.flag, 2 * sizeof(int32_t), hipHostMallocCoherent));
         HIPCHK(hipEventCreateWithFlags(&g_poll.ev[0], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&g_poll.ev[1], hipEventDisableTiming));
     }
@@ -298,10 +308,13 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     A.u0 = o->u0; A.v0 = o->v0; A.w0 = o->w0;
     A.force = o->force; A.force_len = o->force_len;
     A.trace_i = o->trace_i; A.trace_d = o->trace_d; A.trace_cap = o->trace_cap;
+    A.host_done = g_poll.flag;
     A.ws = w;
 
-    // --- the iteration loop, enqueued in chunks; the host polls the done
-    // flag of the previous chunk while the next one runs.
+    // --- the iteration loop, enqueued in chunks; the decider sets a pinned
+    // host flag when the solve finishes, and the host reads it after the
+    // previous chunk has completed while the next one runs (no copy is
+    // enqueued between chunks)
     const int chunk = o->check_every > 0 ? o->check_every : 16;
     if (o->algo == POT_ASPOT) {
         A.phase = PH_INIT;
@@ -309,6 +322,7 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     }
     int enq = 0, k = 0;
     bool done = false;
+    *(volatile int32_t*)g_poll.flag = 0;
     hipGraphExec_t gexec = nullptr;
     if (!(o->flags & POT_FLAG_NO_GRAPH) && A.max_iter >= chunk) HIPCHK(chunk_graph(A, o->algo, chunk, &gexec));
     while (!done && enq < A.max_iter) {
@@ -322,11 +336,10 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
         }
         enq += todo;
         const int slot = k & 1;
-        HIPCHK(hipMemcpyAsync(&g_poll.flag[slot], &w.ctl->done, 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(g_poll.ev[slot], st));
         if (k > 0) {
             HIPCHK(hipEventSynchronize(g_poll.ev[slot ^ 1]));
-            done = g_poll.flag[slot ^ 1] != 0;
+            done = *(volatile int32_t*)g_poll.flag != 0;
         }
         ++k;
     }
@@ -386,6 +399,269 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
 
 using namespace pot;
 
+// ---------------------------------------------------------------------------
+// batched solver
+// ---------------------------------------------------------------------------
+// Smallest share of cost entries per group member the autotuner tries; the
+// workspace is sized for the groups it gives.
+constexpr int64_t kMemberMin = 1 << 15;
+static const int64_t kMemberCand[] = {1 << 15, 1 << 16, 1 << 17, 1 << 18};
+
+// members of an instance's group: rows split so that each member sweeps at
+// most `share` entries (and at least 16 rows)
+static int group_size(int n, int m, int64_t share) {
+    int64_t g = ((int64_t)n * m + share - 1) / share;
+    g = std::min<int64_t>(g, kBMaxGroup);
+    g = std::min<int64_t>(g, std::max(1, n / 16));
+    return (int)std::max<int64_t>(1, g);
+}
+
+// workspace of a batch: [queue][descriptors][slots][results][instance regions]
+struct BatchLayout {
+    int64_t desc, slot, res, inst;
+    std::vector<int64_t> off;
+};
+
+static int64_t al256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+static size_t batch_layout(int batch, const pot_problem* probs, BatchLayout* L) {
+    int64_t nslot = 0;
+    for (int k = 0; k < batch; ++k) nslot += group_size(probs[k].n, probs[k].m, kMemberMin);
+    int64_t cur = 256;
+    const int64_t desc = cur;
+    cur += al256((int64_t)sizeof(BDesc) * batch);
+    const int64_t slot = cur;
+    cur += al256((int64_t)sizeof(BSlot) * nslot);
+    const int64_t resb = cur;
+    cur += al256((int64_t)sizeof(pot_result) * batch);
+    const int64_t inst = cur;
+    if (L) {
+        L->desc = desc;
+        L->slot = slot;
+        L->res = resb;
+        L->inst = inst;
+        L->off.resize(batch);
+    }
+    for (int k = 0; k < batch; ++k) {
+        if (L) L->off[k] = cur;
+        cur += blayout(probs[k].n, probs[k].m, group_size(probs[k].n, probs[k].m, kMemberMin)).total;
+    }
+    return (size_t)cur;
+}
+
+static int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+// one launch of the batched kernels (captured as a graph unless disabled)
+struct BGraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+};
+static thread_local BGraphEntry g_bgraphs[4];
+static thread_local int g_bgraph_next = 0;
+
+static hipError_t run_batched(const BArgs& B, int kind, int grid, bool use_graph, hipStream_t st) {
+    if (!use_graph) return launch_batched(B, kind, grid, st);
+    std::string key((const char*)&B, sizeof(B));
+    key.append((const char*)&kind, sizeof(kind));
+    key.append((const char*)&grid, sizeof(grid));
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : g_bgraphs)
+        if (g.exec && g.key == key) exec = g.exec;
+    if (!exec) {
+        if (!g_capture_stream) {
+            hipError_t e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        hipError_t le = launch_batched(B, kind, grid, g_capture_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(g_capture_stream, &graph);
+        if (le != hipSuccess) e = le;
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return e;
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        BGraphEntry& slot = g_bgraphs[g_bgraph_next];
+        g_bgraph_next = (g_bgraph_next + 1) % 4;
+        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+        slot.key = key;
+        slot.exec = exec;
+    }
+    return hipGraphLaunch(exec, st);
+}
+
+// Autotuner of the batched launch: the group share of cost entries per
+// member and the workgroups per CU, timed on the batch itself (3 iterations,
+// no rounding) and cached per batch shape.
+struct BTune {
+    int64_t share;
+    int per_cu;
+};
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int64_t, int64_t, int>, BTune> g_tune;
+
+static pot_status solve_batched(int32_t batch, const pot_problem* probs, const pot_options* o, const pot_warm* warm,
+                                void* wsp, size_t ws_bytes, pot_result* res, double* const* f_out,
+                                double* const* g_out, hipStream_t st) {
+    if (batch < 1 || !probs || !o || !res) return fail(POT_ERR_INVALID_ARG, "batch, probs, opts and res are required");
+    if (!(o->eps > 0.0) || !std::isfinite(o->eps)) return fail(POT_ERR_INVALID_ARG, "eps must be positive");
+    if (o->algo != POT_ASPOT && o->algo != POT_SINKHORN) return fail(POT_ERR_INVALID_ARG, "algo");
+    if (o->block_rule < 0 || o->block_rule > 1 || o->step_rule < 0 || o->step_rule > 1)
+        return fail(POT_ERR_INVALID_ARG, "block_rule and step_rule are 0 or 1");
+    if (o->member_elems < 0) return fail(POT_ERR_INVALID_ARG, "member_elems >= 0");
+    if (o->force || o->trace_i || o->trace_d) return fail(POT_ERR_UNSUPPORTED, "force and trace are single-solve options");
+    const int kind = probs[0].kind;
+    if (kind != POT_COST_F32 && kind != POT_COST_BF16)
+        return fail(POT_ERR_UNSUPPORTED, "pot_solve_batched takes dense FP32 or BF16 costs");
+    int64_t total = 0, largest = 0;
+    for (int k = 0; k < batch; ++k) {
+        const pot_problem& p = probs[k];
+        if (p.kind != kind) return fail(POT_ERR_UNSUPPORTED, "every instance of a batch has the same cost kind");
+        if (p.n < 1 || p.m < 1 || p.n > kBMax || p.m > kBMax)
+            return fail(POT_ERR_INVALID_ARG, "batched instances need 1 <= n, m <= 1024");
+        if (!p.C || !p.r || !p.c) return fail(POT_ERR_INVALID_ARG, "C, r and c are required");
+        if (p.ldc < p.m) return fail(POT_ERR_INVALID_ARG, "ldc < m");
+        if (!(p.s > 0.0) || !std::isfinite(p.s)) return fail(POT_ERR_INVALID_ARG, "s must be positive");
+        if (!std::isfinite(p.cmax)) return fail(POT_ERR_INVALID_ARG, "cmax must be finite");
+        total += (int64_t)p.n * p.m;
+        largest = std::max<int64_t>(largest, (int64_t)p.n * p.m);
+    }
+    BatchLayout L;
+    const size_t need = batch_layout(batch, probs, &L);
+    if (!wsp || ws_bytes < need) return fail(POT_ERR_WORKSPACE, "workspace too small");
+    if (((uintptr_t)wsp) & 255) return fail(POT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    char* base = (char*)wsp;
+    const int cus = device_cus();
+    const int max_per_cu = std::max(1, batched_blocks_per_cu(kind));
+    if (cus <= 0) return fail(POT_ERR_DEVICE, "device query failed");
+
+    // descriptors (largest instance first in the queue)
+    std::vector<int> order(batch);
+    for (int k = 0; k < batch; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)probs[a].n * probs[a].m > (int64_t)probs[b].n * probs[b].m;
+    });
+    auto build = [&](int64_t share, std::vector<BDesc>& desc, std::vector<BSlot>& slots) {
+        desc.assign(batch, BDesc{});
+        slots.clear();
+        for (int k = 0; k < batch; ++k) {
+            const pot_problem& p = probs[k];
+            BDesc& d = desc[k];
+            d.C = p.C;
+            d.ldc = p.ldc;
+            d.r = p.r;
+            d.c = p.c;
+            d.u0 = warm && warm->u0 ? warm->u0[k] : nullptr;
+            d.v0 = warm && warm->v0 ? warm->v0[k] : nullptr;
+            d.w0 = warm && warm->w0 ? warm->w0[k] : 0.0;
+            d.f_out = f_out ? f_out[k] : nullptr;
+            d.g_out = g_out ? g_out[k] : nullptr;
+            d.s = p.s;
+            d.cmax = p.cmax;
+            d.n = p.n;
+            d.m = p.m;
+            d.G = group_size(p.n, p.m, std::max(share, kMemberMin));
+            const int vw = kind == POT_COST_BF16 ? 8 : 4;
+            d.vec = ((p.ldc % vw) == 0 && (((uintptr_t)p.C) & 15) == 0) ? 1 : 0;
+            d.off = L.off[k];
+        }
+        for (int k : order)
+            for (int g = 0; g < desc[k].G; ++g) slots.push_back(BSlot{k, g});
+    };
+    BArgs B;
+    std::memset(&B, 0, sizeof(B));
+    B.desc = (const BDesc*)(base + L.desc);
+    B.slot = (const BSlot*)(base + L.slot);
+    B.batch = batch;
+    B.queue = (int32_t*)base;
+    B.res = (pot_result*)(base + L.res);
+    B.base = base;
+    B.algo = o->algo;
+    B.max_iter = o->max_iter > 0 ? o->max_iter : 100000;
+    B.block_rule = o->block_rule;
+    B.step_rule = o->step_rule;
+    B.warm_check = warm ? warm->check : 0;
+    B.spin_limit = 1 << 24;
+    B.do_round = (o->flags & POT_FLAG_NO_ROUND) ? 0 : 1;
+    B.eps = o->eps;
+    B.gamma_user = o->gamma;
+    B.tol_user = o->tol;
+    B.A_user = o->A;
+    const bool use_graph = !(o->flags & POT_FLAG_NO_GRAPH);
+    std::vector<BDesc> desc;
+    std::vector<BSlot> slots;
+    auto upload = [&](int64_t share) -> hipError_t {
+        build(share, desc, slots);
+        B.nslot = (int32_t)slots.size();
+        hipError_t e = hipMemcpyAsync(base + L.desc, desc.data(), sizeof(BDesc) * batch, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(base + L.slot, slots.data(), sizeof(BSlot) * slots.size(), hipMemcpyHostToDevice, st);
+        return e;
+    };
+
+    BTune tune{o->member_elems > 0 ? (int64_t)o->member_elems : 0, std::min(2, max_per_cu)};
+    if (tune.share == 0) {
+        const auto key = std::make_tuple(kind, batch, total >> 16, largest, o->algo);
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end()) { tune = it->second; have = true; }
+        }
+        if (!have) {
+            // time each candidate on 3 iterations of the batch (no rounding, no outputs)
+            hipEvent_t e0, e1;
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            float best = 1e30f;
+            BTune bt{kMemberCand[0], 1};
+            BArgs T = B;
+            T.max_iter = 3;
+            T.do_round = 0;
+            for (int64_t share : kMemberCand) {
+                for (int per_cu = 1; per_cu <= std::min(2, max_per_cu); ++per_cu) {
+                    HIPCHK(upload(share));
+                    for (auto& d : desc) { d.f_out = nullptr; d.g_out = nullptr; }
+                    HIPCHK(hipMemcpyAsync(base + L.desc, desc.data(), sizeof(BDesc) * batch, hipMemcpyHostToDevice, st));
+                    T.nslot = (int32_t)slots.size();
+                    const int grid = std::max(1, std::min(T.nslot, cus * per_cu));
+                    HIPCHK(hipEventRecord(e0, st));
+                    HIPCHK(launch_batched(T, kind, grid, st));
+                    HIPCHK(hipEventRecord(e1, st));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; bt = BTune{share, per_cu}; }
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            tune = bt;
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = tune;
+        }
+    }
+    HIPCHK(upload(tune.share));
+    const int grid = std::max(1, std::min(B.nslot, cus * tune.per_cu));
+    HIPCHK(run_batched(B, kind, grid, use_graph, st));
+    HIPCHK(hipMemcpyAsync(res, base + L.res, sizeof(pot_result) * batch, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pot_status first = POT_OK;
+    for (int k = 0; k < batch; ++k)
+        if (res[k].status != POT_OK && first == POT_OK) first = (pot_status)res[k].status;
+    if (first != POT_OK) fail(first, "an instance of the batch did not finish with POT_OK (see res[].status)");
+    return first;
+}
+
 extern "C" {
 
 size_t pot_workspace_bytes(const pot_problem* prob, const pot_options* opts) {
@@ -406,26 +682,21 @@ pot_status pot_solve(const pot_problem* prob, const pot_options* opts, void* ws,
 }
 
 size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, const pot_options* opts) {
+    (void)opts;
     if (batch < 1 || !probs) return 0;
-    size_t mx = 0;
-    for (int k = 0; k < batch; ++k) mx = std::max(mx, pot_workspace_bytes(&probs[k], opts));
-    return mx;
+    for (int k = 0; k < batch; ++k)
+        if (probs[k].n < 1 || probs[k].m < 1 || probs[k].n > kBMax || probs[k].m > kBMax) return 0;
+    return batch_layout(batch, probs, nullptr);
 }
 
-pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_options* opts, void* ws,
-                             size_t ws_bytes, pot_result* res, double* const* f_out, double* const* g_out,
-                             void* stream) {
-    if (batch < 1 || !probs || !opts || !res) return fail(POT_ERR_INVALID_ARG, "batch arguments");
-    pot_status first = POT_OK;
-    for (int k = 0; k < batch; ++k) {
-        pot_outputs o;
-        std::memset(&o, 0, sizeof(o));
-        o.f = f_out ? f_out[k] : nullptr;
-        o.g = g_out ? g_out[k] : nullptr;
-        pot_status st = pot_solve(&probs[k], opts, ws, ws_bytes, &res[k], &o, stream);
-        if (st != POT_OK && first == POT_OK) first = st;
+pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_options* opts, const pot_warm* warm,
+                             void* ws, size_t ws_bytes, pot_result* res, double* const* f_out,
+                             double* const* g_out, void* stream) {
+    try {
+        return solve_batched(batch, probs, opts, warm, ws, ws_bytes, res, f_out, g_out, (hipStream_t)stream);
+    } catch (...) {
+        return fail(POT_ERR_DEVICE, "internal error");
     }
-    return first;
 }
 
 pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,

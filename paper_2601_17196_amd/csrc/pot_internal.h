@@ -93,6 +93,7 @@ struct PassArgs {
     double* trace_d;
     int32_t trace_cap;
     double* plan;          // PH_R4 output
+    int32_t* host_done;    // pinned host flag set to 1 by the decider when the solve finishes (or NULL)
     Ws ws;
 };
 
@@ -104,5 +105,62 @@ struct SetupArgs {
     const double* c;
     Ws ws;
 };
+
+// ---------------------------------------------------------------------------
+// batched solver (pot_solve_batched): one persistent launch; an instance is
+// solved by a group of G workgroups ("members") that split its rows
+// ---------------------------------------------------------------------------
+constexpr int kBMax = 1024;           // rows and columns per instance
+constexpr int kBMaxGroup = 8;         // members per instance
+
+struct BDesc {
+    const void* C;                    // dense cost (F32 or BF16), n x m, ld = ldc
+    int64_t ldc;
+    const double* r;
+    const double* c;
+    const double* u0;                 // warm start (n), or NULL
+    const double* v0;                 // warm start (m), or NULL
+    double* f_out;                    // log scalings out (n), or NULL
+    double* g_out;                    // (m), or NULL
+    double s, cmax, w0;
+    int32_t n, m, G, vec;             // vec: 16-byte vector loads of C allowed
+    int64_t off;                      // byte offset of the instance's region in the workspace
+};
+
+struct BSlot {
+    int32_t inst, member;
+};
+
+struct BArgs {
+    const BDesc* desc;
+    const BSlot* slot;                // members of all instances, largest instance first
+    int32_t nslot;
+    int32_t batch;
+    int32_t* queue;                   // next slot to take
+    pot_result* res;                  // per-instance results (device)
+    char* base;                       // workspace base (instance regions)
+    int32_t algo, max_iter, block_rule, step_rule;
+    int32_t warm_check;               // 1: keep a warm start only if phi(z0) < phi(0)
+    int32_t spin_limit;               // bound of every wait of a group barrier
+    int32_t do_round;                 // 0: skip the rounding (timing runs of the autotuner)
+    int32_t pad_;
+    double eps, gamma_user, tol_user, A_user;
+};
+
+// byte layout of one instance's region (the same on the host and the device)
+struct BLayout {
+    int64_t sync, rows, cols, colpart, rowsc, total;
+};
+__host__ __device__ inline BLayout blayout(int n, int m, int G) {
+    auto al = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
+    BLayout L;
+    L.sync = 0;                                          // int32 [2]: barrier count, error
+    L.rows = 256;                                        // 12 FP64 row vectors of length n
+    L.cols = L.rows + al(12 * 8 * (int64_t)n);           // per member: 12 FP64 column vectors of length m
+    L.colpart = L.cols + al(12 * 8 * (int64_t)m) * G;    // FP64 [G][m] column partials
+    L.rowsc = L.colpart + al(8 * (int64_t)m * G);        // FP64 [G][kScal] row-side scalars
+    L.total = L.rowsc + al(8 * (int64_t)kScal * G);
+    return L;
+}
 
 }  // namespace pot

@@ -18,387 +18,9 @@
 
 #include <type_traits>
 
-#include "pot_internal.h"
+#include "pot_device.h"
 
 namespace pot {
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-// Wave reductions with DPP lane moves (VALU only; no LDS round trips).  A
-// double moves as its two 32-bit halves.  `old` is what lanes outside the
-// row mask receive.  Every lane of the wave must be active.
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ double dpp_d(double v, double old) {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ float dpp_f(float v, float old) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
-}
-constexpr int kQuadX1 = 0xB1;      // quad_perm [1, 0, 3, 2]
-constexpr int kQuadX2 = 0x4E;      // quad_perm [2, 3, 0, 1]
-constexpr int kHalfMirror = 0x141; // row_half_mirror
-constexpr int kMirror = 0x140;     // row_mirror
-constexpr int kBcast15 = 0x142;    // row_bcast:15 (lane 15 of a row into the next row)
-constexpr int kBcast31 = 0x143;    // row_bcast:31 (lane 31 into rows 2 and 3)
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
-// fixed combination order: deterministic; the total is returned to every lane
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_d<kQuadX1>(v, 0.0);
-    v += dpp_d<kQuadX2>(v, 0.0);
-    v += dpp_d<kHalfMirror>(v, 0.0);
-    v += dpp_d<kMirror>(v, 0.0);            // every lane: its row's sum
-    v += dpp_d<kBcast15, 0xA>(v, 0.0);      // rows 1, 3 add rows 0, 2
-    v += dpp_d<kBcast31, 0xC>(v, 0.0);      // rows 2, 3 add rows 0 + 1
-    return readlane_d(v, 63);
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-    v += dpp_f<kQuadX1>(v, 0.0f);
-    v += dpp_f<kQuadX2>(v, 0.0f);
-    v += dpp_f<kHalfMirror>(v, 0.0f);
-    v += dpp_f<kMirror>(v, 0.0f);
-    v += dpp_f<kBcast15, 0xA>(v, 0.0f);
-    v += dpp_f<kBcast31, 0xC>(v, 0.0f);
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-    v = fmax(v, dpp_d<kQuadX1>(v, v));
-    v = fmax(v, dpp_d<kQuadX2>(v, v));
-    v = fmax(v, dpp_d<kHalfMirror>(v, v));
-    v = fmax(v, dpp_d<kMirror>(v, v));
-    v = fmax(v, dpp_d<kBcast15, 0xA>(v, v));
-    v = fmax(v, dpp_d<kBcast31, 0xC>(v, v));
-    return readlane_d(v, 63);
-}
-
-// Sum K doubles over the 256 threads of the block (fixed order: deterministic).
-// The result is returned to every thread.
-template <int K>
-__device__ void block_sum(double (&v)[K], double* lds /* >= 4*K */) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = (lds[k] + lds[K + k]) + (lds[2 * K + k] + lds[3 * K + k]);
-    __syncthreads();
-}
-
-// Merge (max, sum-of-exp) pairs: log-sum-exp in two numbers.
-__device__ __forceinline__ void lse_merge(double& m1, double& s1, double m2, double s2) {
-    if (m2 == -INFINITY) return;
-    if (m1 == -INFINITY) { m1 = m2; s1 = s2; return; }
-    if (m2 > m1) { s1 = s1 * exp(m1 - m2) + s2; m1 = m2; }
-    else s1 = s1 + s2 * exp(m2 - m1);
-}
-
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ void lse_step(double& m, double& s) {
-    const double m2 = dpp_d<CTRL, ROW_MASK>(m, -INFINITY), s2 = dpp_d<CTRL, ROW_MASK>(s, 0.0);
-    lse_merge(m, s, m2, s2);
-}
-
-// log-sum-exp pair over the block; the result is returned to every thread
-__device__ void block_lse(double& m, double& s, double* lds) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    lse_step<kQuadX1>(m, s);
-    lse_step<kQuadX2>(m, s);
-    lse_step<kHalfMirror>(m, s);
-    lse_step<kMirror>(m, s);
-    lse_step<kBcast15, 0xA>(m, s);
-    lse_step<kBcast31, 0xC>(m, s);
-    m = readlane_d(m, 63);
-    s = readlane_d(s, 63);
-    if (lane == 0) { lds[2 * wave] = m; lds[2 * wave + 1] = s; }
-    __syncthreads();
-    m = lds[0];
-    s = lds[1];
-    for (int w = 1; w < 4; ++w) lse_merge(m, s, lds[2 * w], lds[2 * w + 1]);
-    __syncthreads();
-}
-
-// two-slot state by parity with constant indices (lets a copy of the control block
-// live in registers)
-__device__ __forceinline__ double pick2(const double (&a)[2], int k) { return k ? a[1] : a[0]; }
-__device__ __forceinline__ void put2(double (&a)[2], int k, double v) {
-    if (k) a[1] = v;
-    else a[0] = v;
-}
-
-// Cross-workgroup data inside one launch (tile partials, the points a strip's
-// writer stores, strip sums) is written with agent-scope stores and read with
-// agent-scope loads, which are coherent across the XCDs' L2 caches; the
-// stores are waited for (s_waitcnt vmcnt(0)) before the arrival counter is
-// incremented.  This avoids an L2 write-back and invalidate in every
-// workgroup, which an agent-scope fence costs.  Data consumed by a later
-// launch needs nothing: the kernel boundary orders it.
-template <typename T>
-__device__ __forceinline__ void st_agent(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// s_waitcnt vmcnt(0): every store of this wave has completed
-__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
-__device__ __forceinline__ double logaddexp(double a, double b) {
-    if (a == -INFINITY) return b;
-    if (b == -INFINITY) return a;
-    double hi = fmax(a, b), lo = fmin(a, b);
-    return hi + log1p(exp(lo - hi));
-}
-
-// rho(a, b) = b - a + a log(a / b) (Section 2.1 notation) as a * h(d),
-// d = b/a - 1, h(d) = d - log(1 + d).  For |d| < 1/2 with y = d / (2 + d):
-// log(1 + d) = 2 atanh(y), so h = 2 y^2 / (1 - y) - 2 y^3 sum_k y^{2k} / (2k + 3),
-// free of cancellation; |y| <= 1/3 and 18 terms leave a relative error below
-// 1e-17.  lb = log b, la = log a.
-__device__ double rho_log(double a, double la, double lb) {
-    const double d = expm1(lb - la);
-    double h;
-    if (fabs(d) < 0.5) {
-        const double y = d / (2.0 + d), y2 = y * y;
-        double p = 1.0 / 39.0;             // k = 18
-#pragma unroll
-        for (int k = 17; k >= 0; --k) p = fma(p, y2, 1.0 / (2 * k + 3));
-        // p = sum_{k=0}^{18} y^{2k} / (2k + 3) (Horner)
-        h = 2.0 * y2 / (1.0 - y) - 2.0 * y * y2 * p;
-    } else {
-        h = d - log1p(d);
-    }
-    return a * h;
-}
-
-// ---------------------------------------------------------------------------
-// cost access
-// ---------------------------------------------------------------------------
-// elements per thread per row: 4 (FP32, points) or 8 (BF16); BC = 64 * VW
-template <int KIND> struct Vw { static constexpr int v = 4; };
-template <> struct Vw<POT_COST_BF16> { static constexpr int v = 8; };
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
-    return __uint_as_float(((uint32_t)b) << 16);
-}
-
-// 2^t for an FP64 exponent t, accurate to about one FP32 ulp whatever |t|:
-// t = k + f with k = rint(t) taken from the low word of t + 1.5 * 2^52 (exact
-// for |t| < 2^31) and f = t - k in [-1/2, 1/2] exact in FP64; 2^f in FP32,
-// then scaled by 2^k.  Rounding t itself to FP32 would cost |t| * 2^-24.
-// Callers keep |t| < 2^31 (the duals are clamped, |G C| is bounded).
-__device__ __forceinline__ float exp2_split(double t) {
-    const double magic = 6755399441055744.0;   // 1.5 * 2^52
-    const double mm = t + magic;
-    const int k = __double2loint(mm);
-    const double f = t - (mm - magic);
-    return ldexpf(__builtin_amdgcn_exp2f((float)f), k);
-}
-
-// Load VW consecutive costs of row i starting at column j (j < m); columns
-// >= m are returned as 0 and their terms are zeroed by the caller.
-template <int KIND>
-__device__ __forceinline__ void load_costs(const PassArgs& A, int i, int j, bool vec_ok, float* c) {
-    constexpr int VW = Vw<KIND>::v;
-    if (KIND == POT_COST_F32) {
-        const float* row = (const float*)A.C + (int64_t)i * A.ldc;
-        if (vec_ok && j + VW <= A.m) {
-            float4 q = *(const float4*)(row + j);
-            c[0] = q.x; c[1] = q.y; c[2] = q.z; c[3] = q.w;
-        } else {
-#pragma unroll
-            for (int k = 0; k < VW; ++k) c[k] = (j + k < A.m) ? row[j + k] : 0.0f;
-        }
-    } else if (KIND == POT_COST_BF16) {
-        const uint16_t* row = (const uint16_t*)A.C + (int64_t)i * A.ldc;
-        if (vec_ok && j + VW <= A.m) {
-            uint4 q = *(const uint4*)(row + j);
-            uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                c[2 * k] = __uint_as_float(w4[k] << 16);
-                c[2 * k + 1] = __uint_as_float(w4[k] & 0xffff0000u);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < VW; ++k) c[k] = (j + k < A.m) ? bf16_to_f32(row[j + k]) : 0.0f;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// points of the passes: the value of a row (u) or column (v) dual variable at
-// the point a pass evaluates, with the state writes of that phase, done by
-// the strip's "writer" workgroup only (every WG of the strip computes the same
-// value).  The candidate state values are loaded first (`load_cand`), before
-// the control block is read, and combined with its scalars afterwards
-// (`eval_point`).  side 0 = rows (u, block u), side 1 = columns (v, block v).
-// ---------------------------------------------------------------------------
-struct SideVecs {
-    const double* init;
-    double *chk0, *chk1, *til0, *til1, *bar, *grave, *z, *d;
-};
-
-__device__ __forceinline__ SideVecs side_vecs(const PassArgs& A, int side) {
-    const Ws& w = A.ws;
-    if (side == 0) return {A.u0, w.uchk0, w.uchk1, w.util0, w.util1, w.ubar, w.ugrave, w.uz, w.du};
-    return {A.v0, w.vchk0, w.vchk1, w.vtil0, w.vtil1, w.vbar, w.vgrave, w.vz, w.dv};
-}
-
-struct Cand {
-    double q0, q1, q2, q3, q4;
-};
-
-// select by value (a conditional on two members would select their addresses
-// and keep the struct in scratch memory)
-__device__ __forceinline__ double sel(int p, double a, double b) { return p ? a : b; }
-
-template <int PH>
-__device__ __forceinline__ Cand load_cand(const PassArgs& A, const SideVecs& V, int side, int i) {
-    Cand q = {0.0, 0.0, 0.0, 0.0, 0.0};
-    switch (PH) {
-    case PH_INIT: q.q0 = V.init ? V.init[i] : 0.0; break;
-    case PH_BAR: q.q0 = V.chk0[i]; q.q1 = V.z[i]; q.q2 = V.d[i]; q.q3 = V.til0[i]; q.q4 = V.til1[i]; break;
-    case PH_GRAVE: q.q0 = V.bar[i]; q.q1 = V.til0[i]; q.q2 = V.til1[i]; q.q3 = V.d[i]; break;
-    case PH_Z: q.q0 = V.grave[i]; q.q1 = V.d[i]; q.q2 = V.chk0[i]; q.q3 = V.chk1[i]; break;
-    case PH_SK_ROW:
-    case PH_SK_COL:
-        if (side == 0) { q.q0 = V.chk0[i]; q.q1 = V.chk1[i]; }   // a^k by parity
-        else q.q0 = V.z[i];                                      // b^k
-        break;
-    default: break;
-    }
-    return q;
-}
-
-template <int PH>
-__device__ __forceinline__ double eval_point(const PassArgs& A, const Ctl& c, const SideVecs& V, const Cand& q,
-                                           int side, int i, bool writer) {
-    const int par = c.t & 1;
-    switch (PH) {
-    case PH_INIT:
-        if (writer) { V.chk0[i] = q.q0; V.til0[i] = q.q0; }
-        return q.q0;
-    case PH_BAR: {
-        // z-check^t = GreenkhornStep(z^{t-1}): d holds this block's delta at z^{t-1}
-        double xc = q.q0;
-        if (c.t != 0) {
-            xc = q.q1 + (c.bchk == side ? q.q2 : 0.0);
-            if (writer) (par ? V.chk1 : V.chk0)[i] = xc;
-        }
-        const double xt = sel(par, q.q4, q.q3);
-        const double xb = (1.0 - c.theta) * xc + c.theta * xt;    // zbar^t
-        if (writer) V.bar[i] = xb;
-        return xb;
-    }
-    case PH_GRAVE: {
-        // z~^{t+1} = base - eta grad phi(zbar); z-grave = zbar + theta (z~^{t+1} - z~^t)
-        const double xb = q.q0, xt = sel(par, q.q2, q.q1), g = q.q3;
-        const double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
-        const double xt1 = (A.step_rule == 0 ? xb : xt) - eta * g;
-        const double xg = xb + c.theta * (xt1 - xt);
-        if (writer) { (par ? V.til0 : V.til1)[i] = xt1; V.grave[i] = xg; }
-        return xg;
-    }
-    case PH_Z: {
-        // z-hat^t = GreenkhornStep(z-grave^t); z^t = argmin phi over {z-check^t, z-hat^t}
-        const double xh = q.q0 + (c.bhat == side ? q.q1 : 0.0);
-        const double z = c.pick ? xh : sel(par, q.q3, q.q2);
-        if (writer) V.z[i] = z;
-        return z;
-    }
-    case PH_SK_ROW: return side == 0 ? sel(par, q.q1, q.q0) : q.q0;   // a^k, b^k
-    case PH_SK_COL: return side == 0 ? sel(par, q.q0, q.q1) : q.q0;   // a^{k+1}, b^k
-    default: return 0.0;
-    }
-}
-
-// scalar w of the point of each ASPOT pass
-template <int PH>
-__device__ __forceinline__ double w_point(const PassArgs& A, const Ctl& c) {
-    const int par = c.t & 1;
-    switch (PH) {
-    case PH_INIT: return A.w0;
-    case PH_BAR: return (1.0 - c.theta) * pick2(c.wchk, par) + c.theta * pick2(c.wtil, par);
-    case PH_GRAVE: return c.wgrave;
-    case PH_Z: return c.wz;
-    default: return 0.0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// per-row and per-column steps of the finalising pass.  The state a step
-// reads is loaded (`load_step`) before the control block, together with the
-// tile partials, so that the pass makes a single round trip to memory.
-// acc slots: 0 T-part, 1 sum e^u, 2 <u, r~>, 3 <du, r~>, 4 rho score,
-//            5 E part, 6 spare, 7 non-finite count
-// ---------------------------------------------------------------------------
-struct StepPre {
-    double x0, x1, x2, x3;
-};
-
-template <int PH>
-__device__ __forceinline__ StepPre load_step(const PassArgs& A, bool row, int i) {
-    const Ws& w = A.ws;
-    StepPre p = {0.0, 0.0, 0.0, 0.0};
-    const double* tv = row ? w.rt : w.ct;          // r~ or c~
-    const double* lv = row ? w.lrt : w.lct;        // their logs
-    switch (PH) {
-    case PH_INIT: p.x0 = (row ? w.uchk0 : w.vchk0)[i]; p.x1 = tv[i]; break;
-    case PH_BAR: p.x0 = (row ? w.ubar : w.vbar)[i]; p.x1 = tv[i]; break;
-    case PH_GRAVE: p.x0 = (row ? w.ugrave : w.vgrave)[i]; p.x1 = tv[i]; p.x2 = lv[i]; break;
-    case PH_Z: p.x0 = (row ? w.uz : w.vz)[i]; p.x1 = tv[i]; p.x2 = lv[i]; break;
-    case PH_SK_ROW: p.x0 = w.uchk0[i]; p.x1 = w.uchk1[i]; p.x2 = w.rt[i]; p.x3 = w.lrt[i]; break;
-    case PH_SK_COL: p.x0 = w.vz[i]; p.x1 = w.lct[i]; break;
-    default: break;
-    }
-    return p;
-}
-
-// ASPOT step of row i (row) or column i: R is the row (column) sum of B at
-// the point of the pass, x0 the dual there, x1 the smoothed mass, x2 its log.
-template <int PH>
-__device__ __forceinline__ void aspot_step(const PassArgs& A, bool row, int i, double R, const StepPre& p,
-                                           double* acc) {
-    const Ws& w = A.ws;
-    const double x = p.x0, t = p.x1;
-    acc[7] += isfinite(R) ? 0.0 : 1.0;
-    if (row) acc[0] += R;
-    switch (PH) {
-    case PH_INIT:
-        acc[1] += exp(x); acc[2] += t * x;
-        break;
-    case PH_BAR:
-        // gradient of phi at zbar (Section 2.1): R + e^u - r~
-        (row ? w.du : w.dv)[i] = R + exp(x) - t;
-        break;
-    case PH_GRAVE:
-    case PH_Z: {
-        const double ex = exp(x), b = R + ex, lb = log(b);
-        const double d = p.x2 - lb;                 // Greenkhorn step: u + log r~ - log(B 1 + e^u)
-        (row ? w.du : w.dv)[i] = d;
-        acc[1] += ex; acc[2] += t * x; acc[3] += t * d;
-        acc[4] += rho_log(t, p.x2, lb);
-        acc[5] += fabs(b - t);
-        break;
-    }
-    default: break;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // the deciding workgroup: scalar logic of the iteration
@@ -415,35 +37,6 @@ __device__ void gather_strips(const double* part, int nstrips, double (&tot)[kSc
     block_sum<kScal>(tot, lds);
 }
 
-__device__ int argmax3(double a, double b, double d) {
-    int k = 0;
-    double best = a;
-    if (b > best) { k = 1; best = b; }
-    if (d > best) k = 2;
-    return k;
-}
-
-// phi after a block step from a point with sums S (Section 2.1 with the
-// stationarity of the updated block, as in the proof of Theorem 3):
-//   u-step: |r~|_1 + sum e^v - <u', r~> - <v, c~> - w s
-//   v-step: |c~|_1 + sum e^u - <u, r~> - <v', c~> - w s
-//   w-step: s + sum e^u + sum e^v - <u, r~> - <v, c~> - w' s
-__device__ double phi_after(const Ctl& c, int block, const double* R, const double* Cc, double w) {
-    switch (block) {
-    case 0: return c.sum_rt + Cc[1] - (R[2] + R[3]) - Cc[2] - w * c.s;
-    case 1: return c.sum_ct + R[1] - R[2] - (Cc[2] + Cc[3]) - w * c.s;
-    default: {
-        double w1 = w + c.log_s - log(R[0]);
-        return c.s + R[1] + Cc[1] - R[2] - Cc[2] - w1 * c.s;
-    }
-    }
-}
-
-__device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const double* Rs, const double* Cs);
-
-// The deciding block: gathers every block's sums (all threads), then thread 0
-// runs the iteration's scalar logic on the LDS snapshot of the control block
-// and the block writes the snapshot back.
 __device__ void decide(const PassArgs& A, Ctl& cs, double* lds) {
     double Rs[kScal], Cs[kScal];
     const bool rows = A.phase != PH_SK_COL;
@@ -479,158 +72,26 @@ __device__ void decide(const PassArgs& A, Ctl& cs, double* lds) {
             else { Cs[1] = mx; Cs[2] = se; }
         }
     }
-    if (threadIdx.x == 0) decide_logic(A, cs, Rs, Cs);
+    if (threadIdx.x == 0) {
+        decide_logic(A, cs, Rs, Cs);
+        // the host polls this flag between chunks of iterations (system
+        // scope: host memory)
+        if (cs.done && A.host_done) __hip_atomic_store(A.host_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     __syncthreads();
     constexpr int kCtlWords = sizeof(Ctl) / 8;
     if (threadIdx.x < kCtlWords)
         reinterpret_cast<uint64_t*>(A.ws.ctl)[threadIdx.x] = reinterpret_cast<const uint64_t*>(&cs)[threadIdx.x];
 }
 
-__device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const double* Rs, const double* Cs) {
-    const bool rows = A.phase != PH_SK_COL;
-    const bool cols = A.phase != PH_SK_ROW;
-    const int t = c.t, par = t & 1;
-    // a non-finite sum, or (ASPOT) a total that underflowed even the FP64
-    // range after the tiles' shifts: the statistics cannot be represented
-    const bool aspot_phase = A.phase == PH_INIT || A.phase == PH_BAR || A.phase == PH_GRAVE || A.phase == PH_Z;
-    const bool bad = (rows && Rs[7] > 0.0) || (cols && Cs[7] > 0.0) ||
-                     (aspot_phase && !(Rs[0] > 0.0 && isfinite(Rs[0])));
-    if (bad) {
-        c.nonfinite = 1;
-        c.status = POT_ERR_NUMERIC;
-        c.done = 1;
-        c.iters = t;
-        return;
-    }
-    switch (A.phase) {
-    case PH_INIT: {
-        c.T = Rs[0];
-        c.phichk = Rs[0] + Rs[1] + Cs[1] - Rs[2] - Cs[2] - A.w0 * c.s;
-        c.wchk[0] = A.w0;
-        c.wtil[0] = A.w0;
-        c.theta = 1.0;
-        c.t = 0;
-        break;
-    }
-    case PH_BAR: {
-        double gw = Rs[0] - c.s;                         // d phi / d w at zbar
-        double wb = (1.0 - c.theta) * pick2(c.wchk, par) + c.theta * pick2(c.wtil, par);
-        double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
-        double wt1 = (A.step_rule == 0 ? wb : pick2(c.wtil, par)) - eta * gw;
-        c.wbar = wb;
-        put2(c.wtil, par ^ 1, wt1);
-        c.wgrave = wb + c.theta * (wt1 - pick2(c.wtil, par));
-        break;
-    }
-    case PH_GRAVE: {
-        double T = Rs[0];
-        double rho_w = rho_log(c.s, c.log_s, log(T));
-        int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w) : (c.cyc++ % 3);
-        if (A.force && t < A.force_len) b = A.force[3 * t + 0];
-        double ph = phi_after(c, b, Rs, Cs, c.wgrave);
-        double wh = c.wgrave + (b == 2 ? c.log_s - log(T) : 0.0);
-        int pick = ph < c.phichk ? 1 : 0;                // argmin, ties keep z-check
-        if (A.force && t < A.force_len) pick = A.force[3 * t + 1];
-        c.bhat = b;
-        c.pick = pick;
-        c.phihat = ph;
-        c.wz = pick ? wh : pick2(c.wchk, par);
-        if (A.trace_i && t < A.trace_cap) {
-            A.trace_i[3 * t + 0] = b;
-            A.trace_i[3 * t + 1] = pick;
-        }
-        if (A.trace_d && t < A.trace_cap) {
-            A.trace_d[4 * t + 1] = c.phichk;
-            A.trace_d[4 * t + 2] = ph;
-            A.trace_d[4 * t + 3] = c.theta;
-        }
-        break;
-    }
-    case PH_Z: {
-        double T = Rs[0];
-        double E = fabs(T - c.s) + Rs[5] + Cs[5];        // E(z^t), Section 3.1
-        c.E = E;
-        c.T = T;
-        if (A.trace_d && t < A.trace_cap) A.trace_d[4 * t + 0] = E;
-        bool stop = E <= c.tol;
-        if (A.force && t < A.force_len) stop = A.force[3 * t + 2] < 0;
-        if (stop) {
-            c.done = 1;
-            c.status = POT_OK;
-            c.iters = t + 1;
-            if (A.trace_i && t < A.trace_cap) A.trace_i[3 * t + 2] = -1;
-            break;
-        }
-        double rho_w = rho_log(c.s, c.log_s, log(T));
-        int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w) : (c.cyc++ % 3);
-        if (A.force && t < A.force_len) b = A.force[3 * t + 2];
-        c.bchk = b;
-        c.phichk = phi_after(c, b, Rs, Cs, c.wz);
-        put2(c.wchk, par ^ 1, c.wz + (b == 2 ? c.log_s - log(T) : 0.0));
-        if (A.trace_i && t < A.trace_cap) A.trace_i[3 * t + 2] = b;
-        c.theta = c.theta * (sqrt(c.theta * c.theta + 4.0) - c.theta) / 2.0;
-        c.t = t + 1;
-        if (t + 1 >= A.max_iter) {
-            // out of iterations: output z^t (its duals are still in the z slots)
-            c.done = 1;
-            c.status = POT_ERR_NO_CONVERGENCE;
-            c.iters = t + 1;
-            c.t = t;
-        }
-        break;
-    }
-    case PH_SK_ROW: {
-        // row error of iterate t-1 (columns are exact after the b update)
-        double ad = pick2(c.ad, par);
-        double rs_d = exp(ad + c.lse_b) + exp(ad + c.bd - c.A / c.gamma);
-        double E = Rs[0] + fabs(rs_d - c.rhat_d);
-        bool stop = false;
-        if (t >= 1) {
-            c.E = E;
-            if (A.trace_d && t - 1 < A.trace_cap) A.trace_d[4 * (t - 1)] = E;
-            stop = E <= c.tol;
-            if (A.force && t - 1 < A.force_len) stop = A.force[3 * (t - 1) + 2] < 0;
-        }
-        if (stop || t >= A.max_iter) {
-            c.done = 1;
-            c.status = stop ? POT_OK : POT_ERR_NO_CONVERGENCE;
-            c.iters = t;
-            c.out_par = par;
-            break;
-        }
-        put2(c.ad, par ^ 1, c.lrhat_d - logaddexp(c.lse_b, c.bd - c.A / c.gamma));
-        c.lse_a = Rs[1] + log(Rs[2]);
-        break;
-    }
-    case PH_SK_COL: {
-        double adn = pick2(c.ad, par ^ 1);
-        c.bd = c.lchat_d - logaddexp(c.lse_a, adn - c.A / c.gamma);
-        c.lse_b = Cs[1] + log(Cs[2]);
-        c.t = t + 1;
-        break;
-    }
-    default: break;
-    }
-}
-
 // Sinkhorn steps of the finalising pass: one row (column) per thread of the
 // first wave; the block's outputs are {error, max, sum of exp, 0.., non-finite}.
 __device__ void sk_row_finalise(const PassArgs& A, const Ctl& c, int i0, int rows, const double* R,
                                 const StepPre& p, double* out, double* lds) {
-    const Ws& w = A.ws;
-    const int par = c.t & 1;
-    double* an = par ? w.uchk0 : w.uchk1;
     double err = 0.0, nonf = 0.0, mx = -INFINITY, se = 0.0;
     const int r = threadIdx.x;
     if (r < rows) {
-        const int i = i0 + r;
-        const double a = par ? p.x1 : p.x0;
-        const double rs = R[r] + exp(a + c.bd);        // dummy column: cost 0
-        err = fabs(rs - p.x2);
-        nonf = (isfinite(R[r]) && rs > 0.0) ? 0.0 : 1.0;
-        const double anew = a + p.x3 - log(rs);        // u <- u + log r^ - log(X^ 1)
-        an[i] = anew;
-        mx = anew;
+        mx = sk_row_update(A.ws, c, i0 + r, R[r], p, err, nonf);
         se = 1.0;
     }
     block_lse(mx, se, lds);
@@ -645,18 +106,10 @@ __device__ void sk_row_finalise(const PassArgs& A, const Ctl& c, int i0, int row
 
 __device__ void sk_col_finalise(const PassArgs& A, const Ctl& c, int j0, int cols, const double* Q,
                                 const StepPre& p, double* out, double* lds) {
-    const Ws& w = A.ws;
-    const int par = c.t & 1;
-    const double adn = pick2(c.ad, par ^ 1);
     double nonf = 0.0, mx = -INFINITY, se = 0.0;
     const int q = threadIdx.x;
     if (q < cols) {
-        const int j = j0 + q;
-        const double cs = Q[q] + exp(adn + p.x0);       // dummy row: cost 0
-        nonf = (isfinite(Q[q]) && cs > 0.0) ? 0.0 : 1.0;
-        const double bnew = p.x0 + p.x1 - log(cs);
-        w.vz[j] = bnew;
-        mx = bnew;
+        mx = sk_col_update(A.ws, c, j0 + q, Q[q], p, nonf);
         se = 1.0;
     }
     block_lse(mx, se, lds);
@@ -1272,85 +725,59 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
     __shared__ double s_v[4];
     Ctl& c = *S.ws.ctl;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const SetupIn in = {S.n, S.m, S.algo, S.s, S.eps, S.gamma_user, S.tol_user, S.A_user, S.cmax, S.cost_scale, S.w0};
+    // block reduction of three sums over the 1024 threads (16 waves)
+    auto reduce3 = [&](double (&v)[3]) {
+        const int lane = tid & 63, wave = tid >> 6;
+        __syncthreads();
+        for (int k = 0; k < 3; ++k) {
+            double x = wave_sum(v[k]);
+            if (lane == 0) s_red[wave * 3 + k] = x;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a[3] = {0, 0, 0};
+            for (int w = 0; w < nt / 64; ++w)
+                for (int k = 0; k < 3; ++k) a[k] += s_red[w * 3 + k];
+            s_v[0] = a[0]; s_v[1] = a[1]; s_v[2] = a[2];
+        }
+        __syncthreads();
+        for (int k = 0; k < 3; ++k) v[k] = s_v[k];
+    };
     // sums and validity of the masses
-    double sr = 0.0, sc = 0.0, bad = 0.0;
+    double v[3] = {0.0, 0.0, 0.0};      // |r|_1, |c|_1, bad entries
     for (int i = tid; i < S.n; i += nt) {
         double x = S.r[i];
-        bad += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
-        sr += x;
+        v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
+        v[0] += x;
     }
     for (int j = tid; j < S.m; j += nt) {
         double x = S.c[j];
-        bad += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
-        sc += x;
+        v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
+        v[1] += x;
     }
-    // block reduction over 1024 threads (16 waves)
-    {
-        const int lane = tid & 63, wave = tid >> 6;
-        double v[3] = {sr, sc, bad};
-        for (int k = 0; k < 3; ++k) {
-            double x = wave_sum(v[k]);
-            if (lane == 0) s_red[wave * 3 + k] = x;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double a[3] = {0, 0, 0};
-            for (int w = 0; w < nt / 64; ++w)
-                for (int k = 0; k < 3; ++k) a[k] += s_red[w * 3 + k];
-            s_v[0] = a[0]; s_v[1] = a[1]; s_v[2] = a[2];
-        }
-        __syncthreads();
-    }
-    sr = s_v[0];
-    sc = s_v[1];
-    bad = s_v[2];
-    const int N = S.n > S.m ? S.n : S.m;
-    double gamma = S.gamma_user > 0.0 ? S.gamma_user : S.eps / (4.0 * log((double)N));
-    double et = S.eps / (8.0 * S.cmax);
-    if (sr > 1.0) et = fmin(et, 8.0 * (sr - S.s) / (sr - 1.0));
-    if (sc > 1.0) et = fmin(et, 8.0 * (sc - S.s) / (sc - 1.0));
-    double tol = S.tol_user > 0.0 ? S.tol_user : et;
-    int valid = 0;
-    if (bad > 0.0) valid = 1;
-    else if (!(S.s > 0.0) || S.s > sr || S.s > sc) valid = 2;
-    else if (!(gamma > 0.0) || !isfinite(gamma)) valid = 3;
-    else if (!(tol > 0.0)) valid = 4;
+    reduce3(v);
+    const double sr = v[0], sc = v[1];
+    double gamma, et, tol;
+    int valid = setup_params(in, sr, sc, v[2], gamma, et, tol);
     // smoothed marginals r~, c~ (and their logs)
-    double srt = 0.0, sct = 0.0, nonpos = 0.0;
+    double u[3] = {0.0, 0.0, 0.0};      // |r~|_1, |c~|_1, non-positive entries
     for (int i = tid; i < S.n; i += nt) {
-        double x = (1.0 - et / 8.0) * S.r[i] + et / (8.0 * S.n);
+        double x = smooth_mass(S.r[i], et, S.n);
         S.ws.rt[i] = x;
         S.ws.lrt[i] = log(x);
-        nonpos += x > 0.0 ? 0.0 : 1.0;
-        srt += x;
+        u[2] += x > 0.0 ? 0.0 : 1.0;
+        u[0] += x;
     }
     for (int j = tid; j < S.m; j += nt) {
-        double x = (1.0 - et / 8.0) * S.c[j] + et / (8.0 * S.m);
+        double x = smooth_mass(S.c[j], et, S.m);
         S.ws.ct[j] = x;
         S.ws.lct[j] = log(x);
-        nonpos += x > 0.0 ? 0.0 : 1.0;
-        sct += x;
+        u[2] += x > 0.0 ? 0.0 : 1.0;
+        u[1] += x;
     }
-    {
-        const int lane = tid & 63, wave = tid >> 6;
-        double v[3] = {srt, sct, nonpos};
-        __syncthreads();
-        for (int k = 0; k < 3; ++k) {
-            double x = wave_sum(v[k]);
-            if (lane == 0) s_red[wave * 3 + k] = x;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double a[3] = {0, 0, 0};
-            for (int w = 0; w < nt / 64; ++w)
-                for (int k = 0; k < 3; ++k) a[k] += s_red[w * 3 + k];
-            s_v[0] = a[0]; s_v[1] = a[1]; s_v[2] = a[2];
-        }
-        __syncthreads();
-    }
-    srt = s_v[0];
-    sct = s_v[1];
-    if (valid == 0 && s_v[2] > 0.0) valid = 5;
+    reduce3(u);
+    if (valid == 0 && u[2] > 0.0) valid = 5;
     // Sinkhorn state a = 0, b = 0 (b lives in vz)
     if (S.algo == POT_SINKHORN) {
         for (int i = tid; i < S.n; i += nt) S.ws.uchk0[i] = 0.0;
@@ -1360,51 +787,7 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
     for (int k = tid; k < S.nx * S.ny; k += nt) S.ws.tshift[k] = 0;
     for (int k = tid; k < S.nx; k += nt) S.ws.colcnt[k] = 0;
     if (tid < 4) S.ws.glob[tid] = 0;
-    if (tid == 0) {
-        c.gamma = gamma;
-        c.tol = tol;
-        c.M = sr + sc - S.s;
-        c.eps = S.eps;
-        c.s = S.s;
-        c.cmax = S.cmax;
-        c.cost_scale = S.cost_scale;
-        c.G = kLog2e * S.cost_scale / gamma;
-        c.sum_r = sr;
-        c.sum_c = sc;
-        c.sum_rt = srt;
-        c.sum_ct = sct;
-        c.log_s = log(S.s);
-        c.A = S.A_user > 0.0 ? S.A_user : 8.0 * S.cmax / S.eps;
-        c.rhat_d = fmax(sct - S.s, 0.0);     // r^ = (r~, |c~|_1 - s)
-        c.chat_d = fmax(srt - S.s, 0.0);     // c^ = (c~, |r~|_1 - s)
-        c.lrhat_d = log(c.rhat_d);
-        c.lchat_d = log(c.chat_d);
-        c.theta = 1.0;
-        c.wchk[0] = c.wchk[1] = S.w0;
-        c.wtil[0] = c.wtil[1] = S.w0;
-        c.wbar = c.wgrave = c.wz = S.w0;
-        c.phichk = c.phihat = 0.0;
-        c.E = INFINITY;
-        c.T = 0.0;
-        c.ad[0] = 0.0;
-        c.ad[1] = 0.0;
-        c.bd = 0.0;
-        c.lse_a = 0.0;
-        c.lse_b = log((double)S.m);
-        c.T2 = c.nq = c.np = c.cost1 = c.pcq = 0.0;
-        c.kappa = 1.0;
-        c.lambda = 0.0;
-        c.cost = c.mass = 0.0;
-        c.t = 0;
-        c.done = valid ? 1 : 0;
-        c.status = valid ? POT_ERR_INVALID_ARG : POT_OK;
-        c.bhat = c.pick = c.bchk = 0;
-        c.iters = 0;
-        c.nonfinite = 0;
-        c.out_par = 0;
-        c.cyc = 0;
-        c.valid = valid;
-    }
+    if (tid == 0) setup_fill(c, in, gamma, tol, sr, sc, u[0], u[1], valid);
 }
 
 // max_ij C_ij and a check that C is finite and >= 0 (dense kinds), or

@@ -49,7 +49,12 @@ class Options(ct.Structure):
                 ("block_rule", ct.c_int32), ("step_rule", ct.c_int32), ("check_every", ct.c_int32),
                 ("flags", ct.c_uint32), ("u0", ct.c_void_p), ("v0", ct.c_void_p), ("w0", ct.c_double),
                 ("force", ct.c_void_p), ("force_len", ct.c_int32), ("trace_i", ct.c_void_p),
-                ("trace_d", ct.c_void_p), ("trace_cap", ct.c_int32), ("tile_rows", ct.c_int32)]
+                ("trace_d", ct.c_void_p), ("trace_cap", ct.c_int32), ("tile_rows", ct.c_int32),
+                ("member_elems", ct.c_int32)]
+
+
+class Warm(ct.Structure):
+    _fields_ = [("u0", ct.c_void_p), ("v0", ct.c_void_p), ("w0", ct.c_void_p), ("check", ct.c_int32)]
 
 
 class Result(ct.Structure):
@@ -92,8 +97,8 @@ def load():
     lib.pot_solve.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
                               ct.POINTER(Result), ct.POINTER(Outputs), ct.c_void_p]
     lib.pot_solve.restype = ct.c_int
-    lib.pot_solve_batched.argtypes = [ct.c_int32, ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p,
-                                      ct.c_size_t, ct.POINTER(Result), ct.POINTER(ct.c_void_p),
+    lib.pot_solve_batched.argtypes = [ct.c_int32, ct.POINTER(Problem), ct.POINTER(Options), ct.POINTER(Warm),
+                                      ct.c_void_p, ct.c_size_t, ct.POINTER(Result), ct.POINTER(ct.c_void_p),
                                       ct.POINTER(ct.c_void_p), ct.c_void_p]
     lib.pot_solve_batched.restype = ct.c_int
     lib.pot_time_pass.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
@@ -156,7 +161,7 @@ def make_problem(r, c, s, C=None, x=None, y=None, kind=None, ldc=None, cost_scal
 
 def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, block_rule=0,
                  step_rule=0, check_every=0, flags=0, u0=None, v0=None, w0=0.0, force=None,
-                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0):
+                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0, member_elems=0):
     o = Options()
     o.algo = int(algo)
     o.max_iter = int(max_iter)
@@ -175,6 +180,7 @@ def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, bl
     o.trace_i, o.trace_d = _ptr(trace_i), _ptr(trace_d)
     o.trace_cap = int(trace_cap)
     o.tile_rows = int(tile_rows)
+    o.member_elems = int(member_elems)
     return o
 
 
@@ -251,34 +257,73 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     return so
 
 
-def solve_batched(problems, eps, algo=ASPOT, stream=None, workspace=None, **opt_kw):
-    """problems: list of dicts with keys r, c, s and C or (x, y) (device tensors).
-    Returns (status, list of result dicts, list of (f, g) tensors)."""
+def batch_problems(problems):
+    """ctypes array of Problem for a list of dicts with keys r, c, s, C (device
+    tensors; optional ldc, kind, cmax)."""
+    probs = (Problem * len(problems))()
+    for k, pr in enumerate(problems):
+        probs[k] = make_problem(pr["r"], pr["c"], pr["s"], C=pr["C"], kind=pr.get("kind"), ldc=pr.get("ldc"),
+                                cmax=pr.get("cmax", 0.0))
+    return probs
+
+
+def workspace_bytes_batched(problems, opts=None) -> int:
+    probs = problems if isinstance(problems, ct.Array) else batch_problems(problems)
+    return int(load().pot_workspace_bytes_batched(len(probs), probs, ct.byref(opts) if opts else None))
+
+
+def solve_batched(problems, eps, algo=ASPOT, u0=None, v0=None, w0=None, warm_check=True, want_duals=True,
+                  stream=None, workspace=None, raise_on_error=False, **opt_kw):
+    """Solve a list of instances through pot_solve_batched (one persistent
+    launch).  problems: list of dicts with keys r, c, s, C (device tensors;
+    optional ldc, kind, cmax).  u0 / v0: optional lists of device FP64
+    tensors (entries may be None), w0: optional list of floats.
+    Returns (status, list of result dicts, list of (f, g) tensors or None)."""
     import torch
     lib = load()
     B = len(problems)
-    probs = (Problem * B)()
-    keep = []
-    for k, pr in enumerate(problems):
-        probs[k] = make_problem(pr["r"], pr["c"], pr["s"], C=pr.get("C"), x=pr.get("x"), y=pr.get("y"),
-                                cost_scale=pr.get("cost_scale", 0.0), cmax=pr.get("cmax", 0.0))
-        keep.append(pr)
+    probs = batch_problems(problems)
     opts = make_options(eps, algo=algo, **opt_kw)
     nbytes = int(lib.pot_workspace_bytes_batched(B, probs, ct.byref(opts)))
+    if nbytes == 0:
+        raise PotError(ERR_INVALID_ARG, "invalid batch sizes")
     dev = problems[0]["r"].device
     if workspace is None or workspace.numel() < nbytes + 256:
         workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
     base = workspace.data_ptr()
     aligned = (base + 255) & ~255
     avail = workspace.numel() - (aligned - base)
-    fs = [torch.empty(p["r"].shape[0], dtype=torch.float64, device=dev) for p in problems]
-    gs = [torch.empty(p["c"].shape[0], dtype=torch.float64, device=dev) for p in problems]
-    fp = (ct.c_void_p * B)(*[t.data_ptr() for t in fs])
-    gp = (ct.c_void_p * B)(*[t.data_ptr() for t in gs])
+    fg = None
+    fp = gp = None
+    if want_duals:
+        fs = [torch.empty(p["r"].shape[0], dtype=torch.float64, device=dev) for p in problems]
+        gs = [torch.empty(p["c"].shape[0], dtype=torch.float64, device=dev) for p in problems]
+        fp = (ct.c_void_p * B)(*[t.data_ptr() for t in fs])
+        gp = (ct.c_void_p * B)(*[t.data_ptr() for t in gs])
+        fg = list(zip(fs, gs))
+    warm = None
+    keep = []
+    if u0 is not None or v0 is not None:
+        warm = Warm()
+        if u0 is not None:
+            ua = (ct.c_void_p * B)(*[_ptr(t) for t in u0])
+            keep.append(ua)
+            warm.u0 = ct.cast(ua, ct.c_void_p)
+        if v0 is not None:
+            va = (ct.c_void_p * B)(*[_ptr(t) for t in v0])
+            keep.append(va)
+            warm.v0 = ct.cast(va, ct.c_void_p)
+        if w0 is not None:
+            wa = (ct.c_double * B)(*[float(x) for x in w0])
+            keep.append(wa)
+            warm.w0 = ct.cast(wa, ct.c_void_p)
+        warm.check = 1 if warm_check else 0
     res = (Result * B)()
-    st = lib.pot_solve_batched(B, probs, ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(avail), res,
-                               fp, gp, _stream_ptr(stream))
-    return int(st), [res[k].as_dict() for k in range(B)], list(zip(fs, gs))
+    st = lib.pot_solve_batched(B, probs, ct.byref(opts), ct.byref(warm) if warm is not None else None,
+                               ct.c_void_p(aligned), ct.c_size_t(avail), res, fp, gp, _stream_ptr(stream))
+    if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
+        raise PotError(st, last_error())
+    return int(st), [res[k].as_dict() for k in range(B)], fg
 
 
 def to_device_instance(inst, device="cuda", kind="f32", pad_ldc=False):

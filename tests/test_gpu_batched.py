@@ -1,0 +1,189 @@
+"""pot_solve_batched (one persistent launch for many instances) against the
+FP64 oracle, through the C ABI.
+
+Bars as for pot_solve: where the oracle and the GPU take the same number of
+iterations the rounded cost agrees to 1e-6 relative (the decisions were the
+same); otherwise both runs stopped at E <= eps~ and the costs agree within
+eps.  The rounded plan's mass is s to 1e-11.
+"""
+import numpy as np
+import pytest
+
+from oracle import potref as O
+from paper_2601_17196_amd import instances as I
+from tests.gpu_common import oracle_cost_matrix, rel
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(37, 300), (300, 37), (64, 64), (129, 257), (5, 9), (200, 180), (1, 50), (512, 40), (1024, 96),
+         (700, 650)]
+
+
+def _insts(sizes, seed0=300, d=3):
+    out = []
+    for k, (n, m) in enumerate(sizes):
+        g = np.random.default_rng(seed0 + k)
+        out.append(I.uniform_pair(n, m, d, seed0 + k, mass_r=float(g.uniform(0.8, 1.2)),
+                                  mass_c=float(g.uniform(0.8, 1.2)), s_frac=float(g.uniform(0.5, 0.9))))
+    return out
+
+
+def _dev(insts, kind="f32"):
+    from paper_2601_17196_amd import pot
+    probs = []
+    for inst in insts:
+        d = pot.to_device_instance(inst, "cuda:0", kind=kind)
+        probs.append(dict(r=d["r"], c=d["c"], s=d["s"], C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0))
+    return probs
+
+
+def _solve(insts, algo="aspot", kind="f32", **kw):
+    import torch
+
+    from paper_2601_17196_amd import pot
+    a = pot.ASPOT if algo == "aspot" else pot.SINKHORN
+    print(f"batched {algo} {kind}: {len(insts)} instances {kw}", flush=True)
+    st, res, fg = pot.solve_batched(_dev(insts, kind), insts[0].eps, algo=a, **kw)
+    torch.cuda.synchronize()
+    return st, res, fg
+
+
+def _check(inst, res, algo, kind="f32", f=None, g=None):
+    ref = O.solve(oracle_cost_matrix(inst, kind), inst.r, inst.c, inst.s, inst.eps, algo=algo, cmax=1.0)
+    assert res["status"] == 0, res
+    assert abs(res["mass"] - inst.s) <= 1e-11 * max(1.0, inst.s)
+    assert res["E"] <= res["tol"]
+    if res["iters"] == ref.iters:
+        assert rel(res["cost"], ref.rounded["cost"]) <= 1e-6, (inst.name, res["cost"], ref.rounded["cost"])
+        if f is not None and algo == "aspot":
+            fe = f.cpu().numpy()
+            assert np.max(np.abs(fe - ref.f)) <= 1e-6 * max(1.0, np.max(np.abs(ref.f)))
+    else:
+        assert abs(res["cost"] - ref.rounded["cost"]) <= inst.eps
+    return ref
+
+
+@pytest.mark.parametrize("algo", ["aspot", "sinkhorn"])
+def test_batched_uneven_matches_oracle(algo):
+    insts = _insts(SIZES)
+    st, res, fg = _solve(insts, algo)
+    assert st == 0
+    same = 0
+    for inst, r, (f, g) in zip(insts, res, fg):
+        ref = _check(inst, r, algo, f=f, g=g)
+        same += r["iters"] == ref.iters
+    assert same >= len(insts) // 2      # most runs take every decision the same way
+
+
+@pytest.mark.parametrize("algo", ["aspot", "sinkhorn"])
+def test_batched_groups_split_rows(algo):
+    """member_elems = 4096 splits every instance above 4096 entries over up to
+    8 workgroups that exchange column partials; the results match the oracle
+    and the unsplit run."""
+    insts = _insts(SIZES[-4:], seed0=400)
+    st1, res1, _ = _solve(insts, algo, member_elems=4096)
+    st2, res2, _ = _solve(insts, algo, member_elems=1 << 22)
+    assert st1 == 0 and st2 == 0
+    for inst, a, b in zip(insts, res1, res2):
+        _check(inst, a, algo)
+        # the split changes which rows share an FP32 accumulation batch: the
+        # two runs agree to the FP32 path's bar, not bitwise
+        if a["iters"] == b["iters"]:
+            assert rel(a["cost"], b["cost"]) <= 1e-6
+
+
+def test_batched_bf16_within_eps():
+    insts = _insts(SIZES[:6], seed0=500)
+    st, res, _ = _solve(insts, "aspot", kind="bf16")
+    assert st == 0
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0
+        ref = O.solve(inst.C64, inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0)
+        assert abs(r["cost"] - ref.rounded["cost"]) <= inst.eps
+        assert abs(r["mass"] - inst.s) <= 1e-11
+
+
+def test_batched_warm_start_at_optimum_and_fallback():
+    """Warm starts at the oracle's converged duals finish in one or two
+    iterations; a poor warm start (phi above phi(0)) is dropped for a cold
+    start and still reaches eps."""
+    import torch
+    insts = _insts([(90, 70), (60, 120), (100, 100)], seed0=600)
+    u0, v0, w0 = [], [], []
+    for k, inst in enumerate(insts):
+        C = inst.C32.astype(np.float64)
+        gam, tol, M, rt, ct_ = O.setup(inst.r, inst.c, inst.s, inst.eps, cmax=1.0)
+        if k < 2:
+            u, v, w, _, _, _, _ = O.aspot(C, gam, 1e-9, rt, ct_, inst.s, M)
+        else:
+            u, v, w = np.full(inst.n, 3.0), np.full(inst.m, 3.0), 0.0   # B(z0) ~ e^6 B(0)
+        u0.append(torch.from_numpy(u).cuda())
+        v0.append(torch.from_numpy(v).cuda())
+        w0.append(float(w))
+    st, res, _ = _solve(insts, "aspot", u0=u0, v0=v0, w0=w0, warm_check=True)
+    assert st == 0
+    for k, (inst, r) in enumerate(zip(insts, res)):
+        assert r["status"] == 0
+        assert abs(r["mass"] - inst.s) <= 1e-11
+        if k < 2:
+            assert r["used_warm"] == 1 and r["iters"] <= 2
+        else:
+            assert r["used_warm"] == 0
+            _check(inst, r, "aspot")
+
+
+def test_batched_invalid_instance_reported_others_solved():
+    from paper_2601_17196_amd import pot
+    insts = _insts([(40, 50), (30, 20), (60, 61)], seed0=700)
+    insts[1].s = 2.0 * max(insts[1].r.sum(), insts[1].c.sum())     # s above the masses
+    st, res, _ = _solve(insts, "aspot")
+    assert st == pot.ERR_INVALID_ARG
+    assert res[1]["status"] == pot.ERR_INVALID_ARG
+    for k in (0, 2):
+        _check(insts[k], res[k], "aspot")
+
+
+def test_batched_rejects_unsupported():
+    import torch
+
+    from paper_2601_17196_amd import pot
+    insts = _insts([(40, 50), (30, 20)], seed0=800)
+    big = I.uniform_pair(1100, 20, 2, 801)
+    with pytest.raises(pot.PotError):
+        pot.solve_batched(_dev([big]), big.eps)
+    probs = _dev(insts)
+    probs[1]["C"] = I.to_bf16_bits(insts[1].C32)
+    probs[1]["C"] = torch.from_numpy(probs[1]["C"].view(np.int16)).cuda()
+    probs[1]["kind"] = pot.COST_BF16
+    probs[1]["ldc"] = insts[1].m
+    st, _, _ = pot.solve_batched(probs, insts[0].eps)
+    assert st == pot.ERR_UNSUPPORTED
+    assert "same cost kind" in pot.last_error()
+
+
+def test_batched_max_iter_still_feasible():
+    from paper_2601_17196_amd import pot
+    insts = _insts([(40, 50), (300, 200)], seed0=900)
+    st, res, _ = _solve(insts, "aspot", max_iter=3)
+    assert st == pot.ERR_NO_CONVERGENCE
+    for inst, r in zip(insts, res):
+        assert r["status"] == pot.ERR_NO_CONVERGENCE and r["iters"] == 3
+        assert abs(r["mass"] - inst.s) <= 1e-11
+        ref = O.solve(inst.C32.astype(np.float64), inst.r, inst.c, inst.s, inst.eps, algo="aspot", cmax=1.0,
+                      max_iter=3)
+        assert rel(r["cost"], ref.rounded["cost"]) <= 1e-6
+
+
+def test_batched_uneven_batch_full_size():
+    """The 512-instance uneven batch (n, m log-uniform in [64, 1024]): every
+    instance reaches E <= eps~ with an exactly feasible rounding; the four
+    smallest are checked against the oracle."""
+    insts = I.c4_batch(512)
+    st, res, _ = _solve(insts, "aspot")
+    assert st == 0
+    for inst, r in zip(insts, res):
+        assert r["status"] == 0 and r["E"] <= r["tol"]
+        assert abs(r["mass"] - inst.s) <= 1e-11 * max(1.0, inst.s)
+    small = sorted(range(len(insts)), key=lambda k: insts[k].n * insts[k].m)[:4]
+    for k in small:
+        _check(insts[k], res[k], "aspot")
