@@ -26,6 +26,11 @@ namespace pot {
 
 namespace {
 
+// 512 threads (8 waves) per workgroup and one workgroup per CU: an instance
+// solved by a single workgroup has two waves on every SIMD.
+constexpr int kBThreads = 512;
+constexpr int kBWaves = kBThreads / 64;
+
 struct Member {
     PassArgs A;              // phase, options and the member's state pointers (A.ws)
     const BDesc* D;
@@ -46,9 +51,9 @@ struct BShared {
     double b[kBMax];         // column offsets (log2 units)
     double R[kBMax];         // row sums of the member's rows (FP64)
     double Q[kBMax];         // column sums (FP64)
-    double colw[4][kBMax];   // per-wave column partials
+    double colw[kBWaves][kBMax];   // per-wave column partials
     double red[64];
-    double lvl[4];
+    double lvl[kBWaves];
     int K;                   // exponent shift of the member's sweep, kept across passes
     int slot, ok, used_warm;
 };
@@ -88,125 +93,168 @@ __device__ bool group_sync(Member& M, BShared& S) {
     return S.ok != 0;
 }
 
+// maximum over the workgroup, returned to every thread
+__device__ double block_max(double v, BShared& S) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_max(v);
+    if (lane == 0) S.lvl[wave] = v;
+    __syncthreads();
+    v = S.lvl[0];
+    for (int w = 1; w < kBWaves; ++w) v = fmax(v, S.lvl[w]);
+    __syncthreads();
+    return v;
+}
+
+// column sum of the per-wave partials (fixed pairwise order)
+__device__ __forceinline__ double colw_sum(const BShared& S, int j) {
+    return wave_tree<kBWaves>(&S.colw[0][j], kBMax);
+}
+
 // Largest |exponent| of the member's terms (used only when every sum of a
 // sweep under- or overflowed).
 template <int KIND>
 __device__ double member_max_exponent(const Member& M, BShared& S, double G2) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double mx = -INFINITY;
-    for (int r = wave; r < M.nr; r += 4) {
+    for (int r = wave; r < M.nr; r += kBWaves) {
         const int i = M.r0 + r;
         for (int j = lane; j < M.m; j += 64) mx = fmax(mx, fma(bcost64<KIND>(M, i, j), -G2, S.a[r] + S.b[j]));
     }
-    mx = wave_max(mx);
-    if (lane == 0) S.lvl[wave] = mx;
-    __syncthreads();
-    mx = fmax(fmax(S.lvl[0], S.lvl[1]), fmax(S.lvl[2], S.lvl[3]));
-    __syncthreads();
-    return mx;
+    return block_max(mx, S);
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));   // 16 bytes: 4 FP32 or 8 BF16 costs
+
+// Costs of one row chunk for this lane: VW consecutive columns from jb.  A
+// full chunk (uniform condition) takes one 16-byte load; the last, partial
+// chunk takes VW element loads at clamped (always valid) addresses, masked
+// later, so that no load is divergent.
+template <int KIND, int VW>
+__device__ __forceinline__ f32x4 load_chunk(const char* rowp, int jb, int m, bool full) {
+    constexpr int EB = (KIND == POT_COST_BF16) ? 2 : 4;
+    if (full) return *(const f32x4*)(rowp + (int64_t)jb * EB);
+    f32x4 q;
+    if constexpr (KIND == POT_COST_BF16) {
+        uint32_t h[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = ((const uint16_t*)rowp)[min(jb + e, m - 1)];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = __uint_as_float(h[2 * e] | (h[2 * e + 1] << 16));
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = ((const float*)rowp)[min(jb + e, m - 1)];
+    }
+    return q;
+}
+
+template <int KIND, int VW>
+__device__ __forceinline__ void unpack_chunk(const f32x4& q, float (&cv)[VW]) {
+    if constexpr (KIND == POT_COST_BF16) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t wv = __float_as_uint(q[e]);
+            cv[2 * e] = __uint_as_float(wv << 16);
+            cv[2 * e + 1] = __uint_as_float(wv & 0xffff0000u);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cv[e] = q[e];
+    }
 }
 
 // One sweep of the member's rows: row sums into S.R (relative to 2^K), column
 // partials into per-thread FP64 accumulators; returns the member's level (the
-// largest row or column sum relative to 2^K).
+// largest row or column sum relative to 2^K).  Wave w takes rows w,
+// w + kBWaves, ... in steps of U rows; the costs of the next step are loaded
+// while the current one is computed.
 template <int KIND, int VW, int KC>
 __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd, const double (&b)[KC][VW],
                                double (&colacc)[KC][VW]) {
     constexpr int CW = 64 * VW;
+    constexpr int U = 8 / KC;                       // rows per step
     constexpr int EB = (KIND == POT_COST_BF16) ? 2 : 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = M.m;
     const bool vec = M.D->vec != 0;
     const char* Cb = (const char*)M.A.C;
+    const int64_t rstride = M.A.ldc * EB;
+    const int nq = (M.nr - wave + kBWaves - 1) / kBWaves;   // rows of this wave
     double lvl = 0.0;
 #pragma unroll
     for (int k = 0; k < KC; ++k)
 #pragma unroll
         for (int e = 0; e < VW; ++e) colacc[k][e] = 0.0;
-    // two rows of the wave per step: rows r and r + 4
-    for (int r = wave; r < M.nr; r += 8) {
-        const bool two = r + 4 < M.nr;
-        float cv[2][KC][VW];
+    if (nq > 0) {
+        f32x4 cur[U][KC], nxt[U][KC];
+        auto fetch = [&](int s, f32x4 (&buf)[U][KC]) __attribute__((always_inline)) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = M.r0 + r + 4 * h;
-            const char* rowp = Cb + ((int64_t)(two || h == 0 ? i : M.r0 + r) * M.A.ldc) * EB;
+            for (int u = 0; u < U; ++u) {
+                const int q = min(s * U + u, nq - 1);
+                const char* rowp = Cb + (int64_t)(M.r0 + wave + kBWaves * q) * rstride;
+#pragma unroll
+                for (int k = 0; k < KC; ++k) {
+                    const int jb = min(k * CW + lane * VW, m - 1);
+                    const bool full = vec && (k + 1) * CW <= m;
+                    buf[u][k] = load_chunk<KIND, VW>(rowp, jb, m, full);
+                }
+            }
+        };
+        fetch(0, cur);
+        for (int s = 0; s * U < nq; ++s) {
+            if ((s + 1) * U < nq) fetch(s + 1, nxt);
+            double rsum[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rsum[u] = 0.0;
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
-                const int jb = k * CW + lane * VW;
-                if (vec && jb + VW <= m) {
-                    typedef float f32x4 __attribute__((ext_vector_type(4)));
-                    const f32x4 q = *(const f32x4*)(rowp + (int64_t)jb * EB);
-                    if constexpr (KIND == POT_COST_BF16) {
+                float col32[VW];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const uint32_t wv = __float_as_uint(q[e]);
-                            cv[h][k][2 * e] = __uint_as_float(wv << 16);
-                            cv[h][k][2 * e + 1] = __uint_as_float(wv & 0xffff0000u);
-                        }
-                    } else {
+                for (int e = 0; e < VW; ++e) col32[e] = 0.0f;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) cv[h][k][e] = q[e];
-                    }
-                } else {
+                for (int u = 0; u < U; ++u) {
+                    const int q = s * U + u;
+                    const bool rv = q < nq;
+                    const double ar = S.a[wave + kBWaves * min(q, nq - 1)] - Kd;
+                    float cv[VW];
+                    unpack_chunk<KIND, VW>(cur[u][k], cv);
+                    float rs = 0.0f;
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
-                        const int j = jb + e;
-                        float x = 0.0f;
-                        if (j < m) {
-                            if constexpr (KIND == POT_COST_BF16) x = bf16_to_f32(((const uint16_t*)rowp)[j]);
-                            else x = ((const float*)rowp)[j];
-                        }
-                        cv[h][k][e] = x;
+                        const int j = k * CW + lane * VW + e;
+                        float ex;
+                        if constexpr (KIND == POT_COST_BF16)
+                            ex = __builtin_amdgcn_exp2f(fmaf(cv[e], -(float)G2, (float)ar + (float)b[k][e]));
+                        else
+                            ex = exp2_split(fma((double)cv[e], -G2, ar + b[k][e]));
+                        ex = (rv && j < m) ? ex : 0.0f;
+                        rs += ex;
+                        col32[e] += ex;
                     }
+                    rsum[u] += (double)rs;
                 }
-            }
-        }
-        double rsum[2] = {0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-            float col32[VW];
-#pragma unroll
-            for (int e = 0; e < VW; ++e) col32[e] = 0.0f;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const double ar = S.a[r + (two ? 4 * h : 0)] - Kd;
-                float rs = 0.0f;
-#pragma unroll
-                for (int e = 0; e < VW; ++e) {
-                    const int j = k * CW + lane * VW + e;
-                    float ex;
-                    if constexpr (KIND == POT_COST_BF16)
-                        ex = __builtin_amdgcn_exp2f(fmaf(cv[h][k][e], -(float)G2, (float)ar + (float)b[k][e]));
-                    else
-                        ex = exp2_split(fma((double)cv[h][k][e], -G2, ar + b[k][e]));
-                    ex = (j < m && (h == 0 || two)) ? ex : 0.0f;
-                    rs += ex;
-                    col32[e] += ex;
-                }
-                rsum[h] += (double)rs;
+                for (int e = 0; e < VW; ++e) colacc[k][e] += (double)col32[e];
             }
 #pragma unroll
-            for (int e = 0; e < VW; ++e) colacc[k][e] += (double)col32[e];
+            for (int u = 0; u < U; ++u) {
+                const double t = wave_sum(rsum[u]);
+                const int q = s * U + u;
+                if (q < nq) {
+                    if (lane == 0) S.R[wave + kBWaves * q] = t;
+                    lvl = fmax(lvl, t);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < KC; ++k) cur[u][k] = nxt[u][k];
         }
-        rsum[0] = wave_sum(rsum[0]);
-        rsum[1] = wave_sum(rsum[1]);
-        if (lane == 0) {
-            S.R[r] = rsum[0];
-            if (two) S.R[r + 4] = rsum[1];
-        }
-        lvl = fmax(lvl, fmax(rsum[0], two ? rsum[1] : 0.0));
     }
 #pragma unroll
     for (int k = 0; k < KC; ++k)
 #pragma unroll
         for (int e = 0; e < VW; ++e) lvl = fmax(lvl, colacc[k][e]);
-    lvl = wave_max(lvl);
-    if (lane == 0) S.lvl[wave] = lvl;
-    __syncthreads();
-    lvl = fmax(fmax(S.lvl[0], S.lvl[1]), fmax(S.lvl[2], S.lvl[3]));
-    __syncthreads();
-    return lvl;
+    return block_max(lvl, S);
 }
 
 // One pass of the algorithm on the member's share of the instance: the point
@@ -214,13 +262,12 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
 // steps, the row-side scalar exchange and the decisions (thread 0, on the
 // member's copy of the control block).  Returns false if a group barrier
 // failed.
-template <int KIND, int PH>
+template <int KIND, int KC, int PH>
 __device__ bool member_pass(Member& M, BShared& S) {
     constexpr bool ROWS = PH != PH_SK_COL;
     constexpr bool COLS = PH != PH_SK_ROW;
     constexpr int VW = (KIND == POT_COST_BF16) ? 8 : 4;
     constexpr int CW = 64 * VW;
-    constexpr int KC = (kBMax + CW - 1) / CW;
     PassArgs& A = M.A;
     const Ctl& c = S.ctl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -230,12 +277,12 @@ __device__ bool member_pass(Member& M, BShared& S) {
     // ---- the point of the pass, clamped as in the tile kernel
     constexpr double kClamp = 536870912.0;  // 2^29
     const double wp = w_point<PH>(A, c);
-    for (int r = tid; r < nr; r += kThreads) {
+    for (int r = tid; r < nr; r += kBThreads) {
         const int i = r0 + r;
         const Cand q = load_cand<PH>(A, RV, 0, i);
         S.a[r] = fmin(fmax((eval_point<PH>(A, c, RV, q, 0, i, true) + wp) * kLog2e, -kClamp), kClamp);
     }
-    for (int j = tid; j < m; j += kThreads) {
+    for (int j = tid; j < m; j += kBThreads) {
         const Cand q = load_cand<PH>(A, CV, 1, j);
         S.b[j] = fmin(fmax(eval_point<PH>(A, c, CV, q, 1, j, true) * kLog2e, -kClamp), kClamp);
     }
@@ -282,16 +329,16 @@ __device__ bool member_pass(Member& M, BShared& S) {
     __syncthreads();
     if (tid == 0) S.K = K;
     if (ROWS)
-        for (int r = tid; r < nr; r += kThreads) S.R[r] *= scale_d;
+        for (int r = tid; r < nr; r += kBThreads) S.R[r] *= scale_d;
     if (COLS) {
-        for (int j = tid; j < m; j += kThreads) {
-            const double q = ((S.colw[0][j] + S.colw[1][j]) + (S.colw[2][j] + S.colw[3][j])) * scale_d;
+        for (int j = tid; j < m; j += kBThreads) {
+            const double q = colw_sum(S, j) * scale_d;
             if (M.G == 1) S.Q[j] = q;
             else st_agent(&M.colpart[(int64_t)M.mem * m + j], q);
         }
         if (M.G > 1) {
             if (!group_sync(M, S)) return false;
-            for (int j = tid; j < m; j += kThreads) {
+            for (int j = tid; j < m; j += kBThreads) {
                 double q = 0.0;
                 for (int g = 0; g < M.G; ++g) q += ld_agent(&M.colpart[(int64_t)g * m + j]);
                 S.Q[j] = q;
@@ -306,33 +353,33 @@ __device__ bool member_pass(Member& M, BShared& S) {
     for (int k = 0; k < kScal; ++k) { Rs[k] = 0.0; Cs[k] = 0.0; }
     if constexpr (PH == PH_SK_ROW) {
         double err = 0.0, nonf = 0.0, mx = -INFINITY, se = 0.0;
-        for (int r = tid; r < nr; r += kThreads) {
+        for (int r = tid; r < nr; r += kBThreads) {
             const int i = r0 + r;
             const double an = sk_row_update(A.ws, c, i, S.R[r], load_step<PH>(A, true, i), err, nonf);
             lse_merge(mx, se, an, 1.0);
         }
-        block_lse(mx, se, S.red);
+        block_lse<kBWaves>(mx, se, S.red);
         double v[2] = {err, nonf};
-        block_sum<2>(v, S.red);
+        block_sum<2, kBWaves>(v, S.red);
         Rs[0] = v[0]; Rs[1] = mx; Rs[2] = se; Rs[7] = v[1];
     } else if constexpr (PH == PH_SK_COL) {
         double nonf = 0.0, mx = -INFINITY, se = 0.0;
-        for (int j = tid; j < m; j += kThreads) {
+        for (int j = tid; j < m; j += kBThreads) {
             const double bn = sk_col_update(A.ws, c, j, S.Q[j], load_step<PH>(A, false, j), nonf);
             lse_merge(mx, se, bn, 1.0);
         }
-        block_lse(mx, se, S.red);
+        block_lse<kBWaves>(mx, se, S.red);
         double v[1] = {nonf};
-        block_sum<1>(v, S.red);
+        block_sum<1, kBWaves>(v, S.red);
         Cs[1] = mx; Cs[2] = se; Cs[7] = v[0];
     } else {
-        for (int r = tid; r < nr; r += kThreads) {
-            const int i = r0 + r;
-            aspot_step<PH>(A, true, i, S.R[r], load_step<PH>(A, true, i), Rs);
+        // rows and columns side by side (one element per thread at the sizes of a batch)
+        for (int k = tid; k < nr + m; k += kBThreads) {
+            if (k < nr) aspot_step<PH>(A, true, r0 + k, S.R[k], load_step<PH>(A, true, r0 + k), Rs);
+            else aspot_step<PH>(A, false, k - nr, S.Q[k - nr], load_step<PH>(A, false, k - nr), Cs);
         }
-        for (int j = tid; j < m; j += kThreads) aspot_step<PH>(A, false, j, S.Q[j], load_step<PH>(A, false, j), Cs);
-        block_sum<kScal>(Rs, S.red);
-        block_sum<kScal>(Cs, S.red);
+        block_sum<kScal, kBWaves>(Rs, S.red);
+        block_sum<kScal, kBWaves>(Cs, S.red);
     }
     // ---- row-side scalars of the whole instance (fixed member order)
     if (ROWS && M.G > 1) {
@@ -372,32 +419,29 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
     const int n = M.n, m = M.m;
     const Ws& w = M.A.ws;
     double v[3] = {0.0, 0.0, 0.0};      // |r|_1, |c|_1, bad masses
-    for (int i = tid; i < n; i += kThreads) {
+    for (int i = tid; i < n; i += kBThreads) {
         const double x = D.r[i];
         v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
         v[0] += x;
     }
-    for (int j = tid; j < m; j += kThreads) {
+    for (int j = tid; j < m; j += kBThreads) {
         const double x = D.c[j];
         v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
         v[1] += x;
     }
-    block_sum<3>(v, S.red);
+    block_sum<3, kBWaves>(v, S.red);
     double cmax = D.cmax;
     int bad_cost = 0;
     if (!(cmax > 0.0)) {
         double mx = 0.0, nb = 0.0;
-        for (int64_t e = tid; e < (int64_t)n * m; e += kThreads) {
+        for (int64_t e = tid; e < (int64_t)n * m; e += kBThreads) {
             const double x = bcost64<KIND>(M, (int)(e / m), (int)(e % m));
             if (!(x >= 0.0) || !isfinite(x)) nb += 1.0;
             else mx = fmax(mx, x);
         }
-        mx = wave_max(mx);
-        if (lane == 0) S.lvl[wave] = mx;
+        cmax = block_max(mx, S);
         double q[1] = {nb};
-        block_sum<1>(q, S.red);
-        cmax = fmax(fmax(S.lvl[0], S.lvl[1]), fmax(S.lvl[2], S.lvl[3]));
-        __syncthreads();
+        block_sum<1, kBWaves>(q, S.red);
         bad_cost = q[0] > 0.0 || !(cmax > 0.0);
     }
     const SetupIn in = {n, m, B.algo, D.s, B.eps, B.gamma_user, B.tol_user, B.A_user, cmax, 1.0, D.w0};
@@ -407,7 +451,7 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
     // every exponent log2(e) C_ij / gamma must stay below 2^29 (exponent split)
     if (valid == 0 && !(kLog2e * cmax / gamma < 536870912.0)) valid = 7;
     double u[3] = {0.0, 0.0, 0.0};      // |r~|_1, |c~|_1, non-positive entries
-    for (int i = tid; i < n; i += kThreads) {
+    for (int i = tid; i < n; i += kBThreads) {
         const double x = smooth_mass(D.r[i], et, n);
         if (i >= M.r0 && i < M.r0 + M.nr) {
             w.rt[i] = x;
@@ -417,7 +461,7 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
         u[2] += x > 0.0 ? 0.0 : 1.0;
         u[0] += x;
     }
-    for (int j = tid; j < m; j += kThreads) {
+    for (int j = tid; j < m; j += kBThreads) {
         const double x = smooth_mass(D.c[j], et, m);
         w.ct[j] = x;
         w.lct[j] = log(x);
@@ -425,7 +469,7 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
         u[2] += x > 0.0 ? 0.0 : 1.0;
         u[1] += x;
     }
-    block_sum<3>(u, S.red);
+    block_sum<3, kBWaves>(u, S.red);
     if (valid == 0 && u[2] > 0.0) valid = 5;
     if (tid == 0) {
         setup_fill(S.ctl, in, gamma, tol, v[0], v[1], u[0], u[1], valid);
@@ -448,7 +492,7 @@ __device__ bool member_round(Member& M, BShared& S) {
     const double* cm = M.A.c;
     double nonf = 0.0;
     // alpha_i = min(1, r_i / (X~ 1)_i), 0/0 read as 1
-    for (int rr = wave; rr < nr; rr += 4) {
+    for (int rr = wave; rr < nr; rr += kBWaves) {
         const int i = r0 + rr;
         const double fi = w.ubar[i];
         double rs = 0.0;
@@ -465,7 +509,7 @@ __device__ bool member_round(Member& M, BShared& S) {
 #pragma unroll
     for (int k = 0; k < KQ; ++k) cacc[k] = 0.0;
     __syncthreads();
-    for (int rr = wave; rr < nr; rr += 4) {
+    for (int rr = wave; rr < nr; rr += kBWaves) {
         const int i = r0 + rr;
         const double fi = w.ubar[i], al = w.alpha[i];
 #pragma unroll
@@ -480,14 +524,14 @@ __device__ bool member_round(Member& M, BShared& S) {
         if (j < m) S.colw[wave][j] = cacc[k];
     }
     __syncthreads();
-    for (int j = tid; j < m; j += kThreads) {
-        const double q = (S.colw[0][j] + S.colw[1][j]) + (S.colw[2][j] + S.colw[3][j]);
+    for (int j = tid; j < m; j += kBThreads) {
+        const double q = colw_sum(S, j);
         if (M.G == 1) S.Q[j] = q;
         else st_agent(&M.colpart[(int64_t)M.mem * m + j], q);
     }
     if (M.G > 1) {
         if (!group_sync(M, S)) return false;
-        for (int j = tid; j < m; j += kThreads) {
+        for (int j = tid; j < m; j += kBThreads) {
             double q = 0.0;
             for (int g = 0; g < M.G; ++g) q += ld_agent(&M.colpart[(int64_t)g * m + j]);
             S.Q[j] = q;
@@ -496,7 +540,7 @@ __device__ bool member_round(Member& M, BShared& S) {
     __syncthreads();
     // beta_j = min(1, c_j / (X'^T 1)_j); q'_j = c_j - (X''^T 1)_j; T'' and |q'|_1
     double v2[3] = {0.0, 0.0, nonf};
-    for (int j = tid; j < m; j += kThreads) {
+    for (int j = tid; j < m; j += kBThreads) {
         const double cs = S.Q[j];
         const double be = cs > cm[j] ? cm[j] / cs : 1.0;
         w.beta[j] = be;
@@ -507,9 +551,9 @@ __device__ bool member_round(Member& M, BShared& S) {
         v2[1] += q2;
         v2[2] += isfinite(cs) ? 0.0 : 1.0;
     }
-    block_sum<3>(v2, S.red);
+    block_sum<3, kBWaves>(v2, S.red);
     // rows of X'' = diag(alpha) X~ diag(beta): p'_i = r_i - (X'' 1)_i, <C, X''>, C q'
-    for (int rr = wave; rr < nr; rr += 4) {
+    for (int rr = wave; rr < nr; rr += kBWaves) {
         const int i = r0 + rr;
         const double fi = w.ubar[i], al = w.alpha[i];
         double rs = 0.0, rc = 0.0, rq = 0.0;
@@ -534,12 +578,12 @@ __device__ bool member_round(Member& M, BShared& S) {
     }
     __syncthreads();
     double v3[4] = {0.0, 0.0, 0.0, 0.0};   // <C, X''>, |p'|_1, p'^T C q', (spare)
-    for (int rr = tid; rr < nr; rr += kThreads) {
+    for (int rr = tid; rr < nr; rr += kBThreads) {
         v3[0] += S.R[rr];
         v3[1] += S.a[rr];
         v3[2] += S.b[rr];
     }
-    block_sum<4>(v3, S.red);
+    block_sum<4, kBWaves>(v3, S.red);
     if (M.G > 1) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -575,8 +619,8 @@ __device__ bool member_round(Member& M, BShared& S) {
     return true;
 }
 
-// one member's share of one instance's solve
-template <int KIND>
+// one member's share of one instance's solve; KC = column chunks of 64 * VW
+template <int KIND, int KC>
 __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
     const BDesc* D = &B.desc[inst];
     const int tid = threadIdx.x;
@@ -634,7 +678,7 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
             const bool warm = D->u0 || D->v0;
             if (warm && B.warm_check) {
                 // keep the warm start only if phi(z0) < phi(0); otherwise start cold
-                ok = member_pass<KIND, PH_INIT>(M, S);
+                ok = member_pass<KIND, KC, PH_INIT>(M, S);
                 // (a warm start whose sums are not representable counts as worse)
                 const double phi_w = S.ctl.done ? INFINITY : S.ctl.phichk;
                 __syncthreads();
@@ -647,7 +691,7 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
                     S.ctl.nonfinite = 0;
                 }
                 __syncthreads();
-                if (ok) ok = member_pass<KIND, PH_INIT>(M, S);
+                if (ok) ok = member_pass<KIND, KC, PH_INIT>(M, S);
                 const double phi_0 = S.ctl.phichk;
                 if (ok && phi_w < phi_0 && !S.ctl.done) {
                     __syncthreads();
@@ -658,36 +702,36 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
                         S.used_warm = 1;
                     }
                     __syncthreads();
-                    ok = member_pass<KIND, PH_INIT>(M, S);
+                    ok = member_pass<KIND, KC, PH_INIT>(M, S);
                 }
             } else {
                 if (tid == 0) S.used_warm = warm ? 1 : 0;
-                ok = member_pass<KIND, PH_INIT>(M, S);
+                ok = member_pass<KIND, KC, PH_INIT>(M, S);
             }
             while (ok && !S.ctl.done) {
-                ok = member_pass<KIND, PH_BAR>(M, S);
+                ok = member_pass<KIND, KC, PH_BAR>(M, S);
                 if (!ok || S.ctl.done) break;
-                ok = member_pass<KIND, PH_GRAVE>(M, S);
+                ok = member_pass<KIND, KC, PH_GRAVE>(M, S);
                 if (!ok || S.ctl.done) break;
-                ok = member_pass<KIND, PH_Z>(M, S);
+                ok = member_pass<KIND, KC, PH_Z>(M, S);
             }
         } else {
             while (ok && !S.ctl.done) {
-                ok = member_pass<KIND, PH_SK_ROW>(M, S);
+                ok = member_pass<KIND, KC, PH_SK_ROW>(M, S);
                 if (!ok || S.ctl.done) break;
-                ok = member_pass<KIND, PH_SK_COL>(M, S);
+                ok = member_pass<KIND, KC, PH_SK_COL>(M, S);
             }
         }
         // form primal: f = u + w (ASPOT) or a (Sinkhorn); g = v or b
         if (ok) {
             const Ctl& c = S.ctl;
-            for (int r = tid; r < M.nr; r += kThreads) {
+            for (int r = tid; r < M.nr; r += kBThreads) {
                 const int i = M.r0 + r;
                 const double f = B.algo == POT_ASPOT ? w.uz[i] + c.wz : (c.out_par ? w.uchk1 : w.uchk0)[i];
                 w.ubar[i] = f;
                 if (D->f_out) D->f_out[i] = f;
             }
-            for (int j = tid; j < m; j += kThreads) {
+            for (int j = tid; j < m; j += kBThreads) {
                 const double g = w.vz[j];
                 w.vbar[j] = g;
                 if (mem == 0 && D->g_out) D->g_out[j] = g;
@@ -719,7 +763,7 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kThreads, 2) void batched_kernel(BArgs B) {
+__global__ __launch_bounds__(kBThreads) void batched_kernel(BArgs B) {
     __shared__ BShared S;
     // every workgroup takes slots until the queue is empty (each instance's
     // loop is bounded by max_iter and every group wait by spin_limit)
@@ -730,7 +774,11 @@ __global__ __launch_bounds__(kThreads, 2) void batched_kernel(BArgs B) {
         __syncthreads();
         if (sl >= B.nslot) return;
         const BSlot slot = B.slot[sl];
-        member_solve<KIND>(B, S, slot.inst, slot.member);
+        constexpr int CW = 64 * ((KIND == POT_COST_BF16) ? 8 : 4);
+        const int m = B.desc[slot.inst].m;
+        if (m <= CW) member_solve<KIND, 1>(B, S, slot.inst, slot.member);
+        else if (m <= 2 * CW) member_solve<KIND, 2>(B, S, slot.inst, slot.member);
+        else member_solve<KIND, (kBMax + CW - 1) / CW>(B, S, slot.inst, slot.member);
     }
 }
 
@@ -750,15 +798,15 @@ __global__ void batched_init(BArgs B) {
 int batched_blocks_per_cu(int kind) {
     int nb = 0;
     hipError_t e = kind == POT_COST_BF16
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel<POT_COST_BF16>, kThreads, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel<POT_COST_F32>, kThreads, 0);
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel<POT_COST_BF16>, kBThreads, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel<POT_COST_F32>, kBThreads, 0);
     return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_batched(const BArgs& B, int kind, int grid, hipStream_t st) {
     batched_init<<<(B.batch + 255) / 256, 256, 0, st>>>(B);
-    if (kind == POT_COST_BF16) batched_kernel<POT_COST_BF16><<<grid, kThreads, 0, st>>>(B);
-    else batched_kernel<POT_COST_F32><<<grid, kThreads, 0, st>>>(B);
+    if (kind == POT_COST_BF16) batched_kernel<POT_COST_BF16><<<grid, kBThreads, 0, st>>>(B);
+    else batched_kernel<POT_COST_F32><<<grid, kBThreads, 0, st>>>(B);
     return hipGetLastError();
 }
 

@@ -74,10 +74,17 @@ __device__ __forceinline__ double wave_max(double v) {
     return readlane_d(v, 63);
 }
 
-// Sum K doubles over the 256 threads of the block (fixed order: deterministic).
+// sum of lds[w * stride] over waves w in [W0, W0 + NW), as a fixed pairwise tree
+template <int NW, int W0 = 0>
+__device__ __forceinline__ double wave_tree(const double* lds, int stride) {
+    if constexpr (NW == 1) return lds[W0 * stride];
+    else return wave_tree<NW / 2, W0>(lds, stride) + wave_tree<NW / 2, W0 + NW / 2>(lds, stride);
+}
+
+// Sum K doubles over the NW waves of the block (fixed order: deterministic).
 // The result is returned to every thread.
-template <int K>
-__device__ inline void block_sum(double (&v)[K], double* lds /* >= 4*K */) {
+template <int K, int NW = 4>
+__device__ inline void block_sum(double (&v)[K], double* lds /* >= NW*K */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
@@ -87,7 +94,7 @@ __device__ inline void block_sum(double (&v)[K], double* lds /* >= 4*K */) {
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = (lds[k] + lds[K + k]) + (lds[2 * K + k] + lds[3 * K + k]);
+    for (int k = 0; k < K; ++k) v[k] = wave_tree<NW>(lds + k, K);
     __syncthreads();
 }
 
@@ -105,8 +112,10 @@ __device__ __forceinline__ void lse_step(double& m, double& s) {
     lse_merge(m, s, m2, s2);
 }
 
-// log-sum-exp pair over the block; the result is returned to every thread
-__device__ inline void block_lse(double& m, double& s, double* lds) {
+// log-sum-exp pair over the NW waves of the block; the result is returned
+// to every thread
+template <int NW = 4>
+__device__ inline void block_lse(double& m, double& s, double* lds /* >= 2*NW */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     lse_step<kQuadX1>(m, s);
     lse_step<kQuadX2>(m, s);
@@ -120,7 +129,7 @@ __device__ inline void block_lse(double& m, double& s, double* lds) {
     __syncthreads();
     m = lds[0];
     s = lds[1];
-    for (int w = 1; w < 4; ++w) lse_merge(m, s, lds[2 * w], lds[2 * w + 1]);
+    for (int w = 1; w < NW; ++w) lse_merge(m, s, lds[2 * w], lds[2 * w + 1]);
     __syncthreads();
 }
 
@@ -157,20 +166,21 @@ __device__ __forceinline__ double logaddexp(double a, double b) {
     return hi + log1p(exp(lo - hi));
 }
 
-// rho(a, b) = b - a + a log(a / b) (Section 2.1 notation) as a * h(d),
-// d = b/a - 1, h(d) = d - log(1 + d).  For |d| < 1/2 with y = d / (2 + d):
-// log(1 + d) = 2 atanh(y), so h = 2 y^2 / (1 - y) - 2 y^3 sum_k y^{2k} / (2k + 3),
-// free of cancellation; |y| <= 1/3 and 18 terms leave a relative error below
-// 1e-17.  lb = log b, la = log a.
-__device__ inline double rho_log(double a, double la, double lb) {
-    const double d = expm1(lb - la);
+// rho(a, b) = b - a + a log(a / b) (Section 2.1 notation) as a * h(d) with
+// d = (b - a) / a and h(d) = d - log(1 + d).  For |d| < 1/10, with
+// y = d / (2 + d) (|y| < 0.048): log(1 + d) = 2 atanh(y), so
+// h = 2 y^2 / (1 - y) - 2 y^3 sum_k y^{2k} / (2k + 3), free of cancellation;
+// 9 terms leave a relative error below 1e-17, and b - a is exact there
+// (b within a factor 2 of a).  Otherwise d - log1p(d) loses at most a factor
+// of about 20 to cancellation.
+__device__ inline double rho_ab(double a, double b) {
+    const double d = (b - a) / a;
     double h;
-    if (fabs(d) < 0.5) {
+    if (fabs(d) < 0.1) {
         const double y = d / (2.0 + d), y2 = y * y;
-        double p = 1.0 / 39.0;             // k = 18
+        double p = 1.0 / 19.0;             // k = 8
 #pragma unroll
-        for (int k = 17; k >= 0; --k) p = fma(p, y2, 1.0 / (2 * k + 3));
-        // p = sum_{k=0}^{18} y^{2k} / (2k + 3) (Horner)
+        for (int k = 7; k >= 0; --k) p = fma(p, y2, 1.0 / (2 * k + 3));
         h = 2.0 * y2 / (1.0 - y) - 2.0 * y * y2 * p;
     } else {
         h = d - log1p(d);
@@ -385,7 +395,7 @@ __device__ __forceinline__ void aspot_step(const PassArgs& A, bool row, int i, d
         const double d = p.x2 - lb;                 // Greenkhorn step: u + log r~ - log(B 1 + e^u)
         (row ? w.du : w.dv)[i] = d;
         acc[1] += ex; acc[2] += t * x; acc[3] += t * d;
-        acc[4] += rho_log(t, p.x2, lb);
+        acc[4] += rho_ab(t, b);
         acc[5] += fabs(b - t);
         break;
     }
@@ -458,7 +468,7 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
     }
     case PH_GRAVE: {
         double T = Rs[0];
-        double rho_w = rho_log(c.s, c.log_s, log(T));
+        double rho_w = rho_ab(c.s, T);
         int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w) : (c.cyc++ % 3);
         if (A.force && t < A.force_len) b = A.force[3 * t + 0];
         double ph = phi_after(c, b, Rs, Cs, c.wgrave);
@@ -495,7 +505,7 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
             if (A.trace_i && t < A.trace_cap) A.trace_i[3 * t + 2] = -1;
             break;
         }
-        double rho_w = rho_log(c.s, c.log_s, log(T));
+        double rho_w = rho_ab(c.s, T);
         int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w) : (c.cyc++ % 3);
         if (A.force && t < A.force_len) b = A.force[3 * t + 2];
         c.bchk = b;
