@@ -25,6 +25,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20          # the plain copy of the counter-scale probe (bytes read, and written)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "stats_pass_c2_4096_f32_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the tile kernel from the committed counter
+    summary, or None when it is missing or was taken on other kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    from paper_2601_17196_amd import profile_summary as PS
+    s = json.load(open(PMC_SUMMARY))
+    if s.get("kernel_source_hash") != PS.kernel_source_hash():
+        return None
+    return s.get("traffic_bytes")
 
 
 def log(*a):
@@ -65,6 +79,99 @@ def time_solves(pot, d, eps, algo, kind, steps, warmup, workspace):
     return outs, wall, ev_ms
 
 
+def _batch_probs(pot, insts, dev):
+    probs = []
+    for inst in insts:
+        d = pot.to_device_instance(inst, dev, kind="f32", pad_ldc=True)
+        probs.append(dict(r=d["r"], c=d["c"], s=d["s"], C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0))
+    return probs
+
+
+def _timed(fn, reps):
+    import torch
+    fn()                                   # warm-up (first call also autotunes the batched launch)
+    torch.cuda.synchronize()
+    best, out = None, None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    return best, out
+
+
+def bench_batched(pot, I, dev, eps, reps, plain_sample):
+    """The uneven batch (512 instances, n, m log-uniform in [64, 1024]):
+    pot_solve_batched against sequential pot_solve calls on a sample."""
+    import numpy as np
+    import torch
+    insts = I.c4_batch(512)
+    probs = _batch_probs(pot, insts, dev)
+    ws = torch.empty(pot.workspace_bytes_batched(probs) + 512, dtype=torch.uint8, device=dev)
+    t, (st, res, _) = _timed(lambda: pot.solve_batched(probs, eps, workspace=ws, want_duals=False), reps)
+    its = np.array([r["iters"] for r in res])
+    ok = all(r["status"] == 0 for r in res)
+    sample = list(range(0, len(insts), len(insts) // plain_sample))[:plain_sample]
+
+    def plain():
+        for j in sample:
+            pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0, want_factors=False)
+    tp, _ = _timed(plain, 1)
+    out = {"instances": len(insts), "solves_per_s": len(insts) / (t / 1e3), "ms": t, "all_ok": ok,
+           "iters_median": float(np.median(its)), "iters_max": int(its.max()),
+           "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample)}
+    del ws, probs
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_warm(pot, I, dev, eps, reps, plain_sample):
+    """The learned warm start on the n = m = 256 mixture batch (1024
+    instances): inference + warm-started batched ASPOT against cold batched
+    ASPOT and sequential plain solves (sample)."""
+    import numpy as np
+    import torch
+    insts = I.c5_batch(1024)
+    probs = _batch_probs(pot, insts, dev)
+    pts = [dict(x=torch.from_numpy(np.ascontiguousarray(i.x, dtype=np.float32)).to(dev),
+                y=torch.from_numpy(np.ascontiguousarray(i.y, dtype=np.float32)).to(dev),
+                r=p["r"], c=p["c"], cost_scale=i.cost_scale) for i, p in zip(insts, probs)]
+    ws = torch.empty(pot.workspace_bytes_batched(probs) + 512, dtype=torch.uint8, device=dev)
+    blob = pot.warm_blob(device=dev)
+
+    def warm():
+        preds = pot.warm_predict(pts, eps, blob)
+        return pot.solve_batched(probs, eps, u0=[p[0] for p in preds], v0=[p[1] for p in preds],
+                                 w0=[0.0] * len(preds), warm_check=True, workspace=ws, want_duals=False)
+    tc, (stc, resc, _) = _timed(lambda: pot.solve_batched(probs, eps, workspace=ws, want_duals=False), reps)
+    tw, (stw, resw, _) = _timed(warm, reps)
+    ti, _ = _timed(lambda: pot.warm_predict(pts, eps, blob), reps)
+    sample = list(range(0, len(insts), len(insts) // plain_sample))[:plain_sample]
+
+    def plain():
+        for j in sample:
+            pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0, want_factors=False)
+    tp, _ = _timed(plain, 1)
+    itc = np.array([r["iters"] for r in resc])
+    itw = np.array([r["iters"] for r in resw])
+    out = {"instances": len(insts),
+           "warm_batched_solves_per_s": len(insts) / (tw / 1e3),
+           "cold_batched_solves_per_s": len(insts) / (tc / 1e3),
+           "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample),
+           "inference_ms": ti, "warm_kept": int(sum(r["used_warm"] for r in resw)),
+           "iters_median_warm": float(np.median(itw)), "iters_median_cold": float(np.median(itc)),
+           "iters_total_warm": int(itw.sum()), "iters_total_cold": int(itc.sum()),
+           "max_cost_gap_warm_vs_cold": float(max(abs(a["cost"] - b["cost"]) for a, b in zip(resw, resc))),
+           "all_ok": all(r["status"] == 0 for r in resw) and all(r["status"] == 0 for r in resc)}
+    del ws, probs, pts
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(inst, iters_full, eps, budget_iters):
     """The FP64 oracle (as it stands) timed on the host cores on a bounded
     sample: `budget_iters` ASPOT iterations of the same instance, scaled to
@@ -100,6 +207,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=32)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="profiling workload only: a 256 MiB device copy (the counters' scale), then one "
+                         "solve and 20 timed statistics passes of the default workload; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the solver has no multi-GPU path in this build "
@@ -115,6 +227,13 @@ def main():
 
     dev = torch.device("cuda:0")
     eps = 1e-2
+    if args.pmc_probe:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log(f"generating workload n=m={args.n}")
     inst = I.c2(0, n=args.n)
     d = pot.to_device_instance(inst, dev, kind=args.kind)
@@ -127,6 +246,16 @@ def main():
     ws = torch.empty(pot.workspace_bytes(prob, pot.make_options(eps, algo=algo)) + 256, dtype=torch.uint8,
                      device=dev)
     log(f"first solve: status {first.status} iters {first.result['iters']} cost {first.result['cost']:.9e}")
+    if args.pmc_probe:
+        kw = dict(u0=first.u, v0=first.v, w0=first.w)
+        if args.kind == "points":
+            pot.time_pass(d["r"], d["c"], d["s"], eps, reps=20, x=d["x"], y=d["y"], cost_scale=d["cost_scale"],
+                          cmax=1.0, **kw)
+        else:
+            pot.time_pass(d["r"], d["c"], d["s"], eps, reps=20, C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0, **kw)
+        torch.cuda.synchronize()
+        log("pmc probe done")
+        return
     outs, wall, ev_ms = time_solves(pot, d, eps, algo, args.kind, args.steps, args.warmup, ws)
     iters = outs[-1].result["iters"]
     ms_per_step = ev_ms / args.steps
@@ -155,7 +284,8 @@ def main():
         alg_bytes = n * m * elem_bytes
         achieved = alg_bytes / (pass_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if args.kind == "f32" and n == 4096 else None}
     log(f"tile kernel: {pass_ms * 1e3:.2f} us/launch -> {achieved:.1f} {roof['unit']}; "
         f"finalising kernel {fin_ms * 1e3:.2f} us")
 
@@ -174,6 +304,16 @@ def main():
             log(f"{name}: {extra[name]}")
             del d2
             torch.cuda.empty_cache()
+
+    if not args.no_batched:
+        log("batched: 512 uneven instances")
+        extra["batched_uneven_512"] = bench_batched(pot, I, dev, eps, 3, args.plain_sample)
+        log(f"batched: {extra['batched_uneven_512']}")
+        from paper_2601_17196_amd import warmstart as W
+        if os.path.exists(W.WEIGHTS):
+            log("warm start: 1024 instances n = m = 256")
+            extra["warm_batched_1024x256"] = bench_warm(pot, I, dev, eps, 2, args.plain_sample)
+            log(f"warm start: {extra['warm_batched_1024x256']}")
 
     cpu = None
     if not args.no_cpu:

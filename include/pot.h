@@ -128,6 +128,7 @@ typedef struct {
     double mass;           /* 1^T Xbar 1 */
     double kappa, lambda, T2;   /* rounding factors (see the header comment) */
     double cost_scale, cmax;
+    double w;              /* ASPOT: w at the output point (Sinkhorn: 0) */
 } pot_result;
 
 typedef struct {
@@ -162,6 +163,15 @@ typedef struct {
                                   it cold (one or two more statistics passes per instance) */
 } pot_warm;
 
+/* Optional per-instance outputs of pot_solve_batched: host arrays of `batch`
+ * device pointers (each array may be NULL, and so may each entry). */
+typedef struct {
+    double* const* f;          /* n_k: X~_ij = exp(f_i + g_j - C_ij / gamma) */
+    double* const* g;          /* m_k */
+    double* const* u;          /* n_k: ASPOT u at the output point (Sinkhorn: a_1..a_n) */
+    double* const* v;          /* m_k: ASPOT v (Sinkhorn: b_1..b_m) */
+} pot_batch_outputs;
+
 /* Workspace for pot_solve_batched over these problems. */
 size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, const pot_options* opts);
 
@@ -176,14 +186,57 @@ size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, cons
  * pointers (cmax <= 0: scanned on the device); opts apply to all (force and
  * trace must be NULL; tile_rows is ignored); warm (may be NULL) gives
  * per-instance warm starts; res (host array of batch) receives the results
- * (used_warm reports whether the warm start was kept); f_out / g_out (host
- * arrays of device pointers, may be NULL, entries may be NULL) receive the
- * log scalings of X~.  Returns POT_OK if every instance is OK, else the
- * first failing status; POT_ERR_DEVICE for an instance whose group of
- * workgroups could not meet (a bounded wait expired). */
+ * (used_warm reports whether the warm start was kept); out (may be NULL)
+ * receives duals.  Returns POT_OK if every instance is OK, else the first
+ * failing status; POT_ERR_DEVICE for an instance whose group of workgroups
+ * could not meet (a bounded wait expired). */
 pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_options* opts,
                              const pot_warm* warm, void* ws, size_t ws_bytes, pot_result* res,
-                             double* const* f_out, double* const* g_out, void* stream);
+                             const pot_batch_outputs* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (a network that predicts ASPOT duals from point clouds;
+ * not in the paper).  Per instance of 2-D points, with mu the mean of its
+ * n + m points and cost C_ij = cost_scale |x_i - y_j|^2:
+ *   features  p_i = ((x_i - mu) sqrt(cost_scale), clip(log(n r_i), -30, 30), 0)
+ *   encoder   h_i = relu(W2 relu(W1 p_i + b1) + b2)                   4 -> 128 -> 128
+ *   context   ctx = mean of h over the side's points
+ *   head      u0_i = (w4 . relu(W3a h_i + W3b ctx_other + b3) + b4) / gamma
+ * and the same for the targets (y, c, m) with the sources' context.  Weights
+ * are BF16 (FP32 biases), products run on the matrix cores with FP32
+ * accumulation.  Weight blob (device memory, 16-byte aligned,
+ * POT_WARM_WEIGHT_BYTES bytes):
+ *   float    b1[128], b2[128], b3[128], w4[128], b4, zero padding to byte 2304
+ *   bfloat16 W1[128][4], W2[128][128], W3a[128][128], W3b[128][128]
+ *            (row-major, output x input; bit patterns, round to nearest even)
+ * The predictions feed pot_solve_batched's warm starts (pot_warm, w0 = 0,
+ * check = 1: the solver takes one exact w step and keeps the prediction
+ * only if it lowers phi below phi(0)).
+ * ------------------------------------------------------------------------- */
+#define POT_WARM_WEIGHT_BYTES 101632
+
+typedef struct {
+    int32_t n, m;          /* points per side, >= 1 */
+    const float* x;        /* (device) n x 2 source points */
+    const float* y;        /* (device) m x 2 target points */
+    const double* r;       /* (device) n source masses */
+    const double* c;       /* (device) m target masses */
+    double cost_scale;     /* > 0: the cost of the solve is cost_scale |x_i - y_j|^2 */
+    double gamma;          /* entropic parameter of the solve; <= 0: eps / (4 ln max(n, m)) */
+    double* u0;            /* (device) n: predicted u, written */
+    double* v0;            /* (device) m: predicted v, written */
+} pot_warm_instance;
+
+/* Workspace of pot_warm_predict for a batch (256-byte aligned device memory). */
+size_t pot_warm_workspace_bytes(int32_t batch);
+
+/* Predict warm starts for `batch` instances (inst: host array).  Work is
+ * enqueued on `stream` (two kernel launches); u0 / v0 are written when the
+ * stream reaches it.  weights: device blob as above.  Writes only the
+ * workspace and the outputs.  POT_ERR_INVALID_ARG on bad sizes, pointers,
+ * cost_scale or alignment (nothing enqueued). */
+pot_status pot_warm_predict(int32_t batch, const pot_warm_instance* inst, double eps, const void* weights,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /* Measurement hook: set up the problem (as pot_solve does) and run the
  * statistics pass (row sums, column sums and total of B at the start point

@@ -8,13 +8,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpot.so")
-SOURCES = ["pot_kernels.hip", "pot_batched.hip", "pot_api.hip"]
+SOURCES = ["pot_kernels.hip", "pot_batched.hip", "pot_warm.hip", "pot_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32) in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-Wl,-z,defs",          # every symbol resolved at link time
 ]
 
 

@@ -29,6 +29,10 @@ hipError_t launch_copy_out(const PassArgs& A, double* alpha, double* beta, doubl
 hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
                               hipEvent_t e3);
 int batched_blocks_per_cu(int kind);
+hipError_t launch_warm(const WDesc* desc_dev, int batch, const void* blob, float* ctx, hipStream_t st);
+size_t warm_desc_bytes();
+void warm_fill_desc(void* dst, const float* x, const float* y, const double* r, const double* c, double* u0,
+                    double* v0, double cost_scale, double inv_gamma, int n, int m);
 hipError_t launch_batched(const BArgs& B, int kind, int grid, hipStream_t st);
 
 static thread_local std::string g_last_error;
@@ -388,7 +392,8 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     res->T2 = hc.T2;
     res->cost_scale = cost_scale;
     res->cmax = cmax;
-    if (out && out->w) *out->w = o->algo == POT_ASPOT ? hc.wz : 0.0;
+    res->w = o->algo == POT_ASPOT ? hc.wz : 0.0;
+    if (out && out->w) *out->w = res->w;
     if (hc.status == POT_ERR_NUMERIC) g_last_error = "non-finite row or column sum (overflow)";
     else if (hc.status == POT_ERR_NO_CONVERGENCE) g_last_error = "max_iter reached before E <= tol";
     else g_last_error.clear();
@@ -510,8 +515,8 @@ static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int64_t, int64_t, int>, BTune> g_tune;
 
 static pot_status solve_batched(int32_t batch, const pot_problem* probs, const pot_options* o, const pot_warm* warm,
-                                void* wsp, size_t ws_bytes, pot_result* res, double* const* f_out,
-                                double* const* g_out, hipStream_t st) {
+                                void* wsp, size_t ws_bytes, pot_result* res, const pot_batch_outputs* out,
+                                hipStream_t st) {
     if (batch < 1 || !probs || !o || !res) return fail(POT_ERR_INVALID_ARG, "batch, probs, opts and res are required");
     if (!(o->eps > 0.0) || !std::isfinite(o->eps)) return fail(POT_ERR_INVALID_ARG, "eps must be positive");
     if (o->algo != POT_ASPOT && o->algo != POT_SINKHORN) return fail(POT_ERR_INVALID_ARG, "algo");
@@ -563,8 +568,10 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
             d.u0 = warm && warm->u0 ? warm->u0[k] : nullptr;
             d.v0 = warm && warm->v0 ? warm->v0[k] : nullptr;
             d.w0 = warm && warm->w0 ? warm->w0[k] : 0.0;
-            d.f_out = f_out ? f_out[k] : nullptr;
-            d.g_out = g_out ? g_out[k] : nullptr;
+            d.f_out = out && out->f ? out->f[k] : nullptr;
+            d.g_out = out && out->g ? out->g[k] : nullptr;
+            d.u_out = out && out->u ? out->u[k] : nullptr;
+            d.v_out = out && out->v ? out->v[k] : nullptr;
             d.s = p.s;
             d.cmax = p.cmax;
             d.n = p.n;
@@ -630,7 +637,7 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
             for (int64_t share : kMemberCand) {
                 for (int per_cu = 1; per_cu <= std::min(2, max_per_cu); ++per_cu) {
                     HIPCHK(upload(share));
-                    for (auto& d : desc) { d.f_out = nullptr; d.g_out = nullptr; }
+                    for (auto& d : desc) { d.f_out = d.g_out = d.u_out = d.v_out = nullptr; }
                     HIPCHK(hipMemcpyAsync(base + L.desc, desc.data(), sizeof(BDesc) * batch, hipMemcpyHostToDevice, st));
                     T.nslot = (int32_t)slots.size();
                     const int grid = std::max(1, std::min(T.nslot, cus * per_cu));
@@ -690,10 +697,10 @@ size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, cons
 }
 
 pot_status pot_solve_batched(int32_t batch, const pot_problem* probs, const pot_options* opts, const pot_warm* warm,
-                             void* ws, size_t ws_bytes, pot_result* res, double* const* f_out,
-                             double* const* g_out, void* stream) {
+                             void* ws, size_t ws_bytes, pot_result* res, const pot_batch_outputs* out,
+                             void* stream) {
     try {
-        return solve_batched(batch, probs, opts, warm, ws, ws_bytes, res, f_out, g_out, (hipStream_t)stream);
+        return solve_batched(batch, probs, opts, warm, ws, ws_bytes, res, out, (hipStream_t)stream);
     } catch (...) {
         return fail(POT_ERR_DEVICE, "internal error");
     }
@@ -749,6 +756,44 @@ pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void*
         if (hc.status != POT_OK) return fail((pot_status)hc.status, "pass reported a non-finite sum");
         *avg_ms = tot / reps;
         if (fin_ms) *fin_ms = tot2 / reps;
+        return POT_OK;
+    } catch (...) {
+        return fail(POT_ERR_DEVICE, "internal error");
+    }
+}
+
+size_t pot_warm_workspace_bytes(int32_t batch) {
+    if (batch < 1) return 0;
+    return (size_t)(al256((int64_t)warm_desc_bytes() * batch) + al256((int64_t)sizeof(float) * 256 * batch));
+}
+
+pot_status pot_warm_predict(int32_t batch, const pot_warm_instance* inst, double eps, const void* weights,
+                            void* ws, size_t ws_bytes, void* stream) {
+    try {
+        if (batch < 1 || !inst) return fail(POT_ERR_INVALID_ARG, "batch >= 1 and inst are required");
+        if (!weights || (((uintptr_t)weights) & 15)) return fail(POT_ERR_INVALID_ARG, "weights: 16-byte aligned device blob");
+        const size_t need = pot_warm_workspace_bytes(batch);
+        if (!ws || ws_bytes < need || (((uintptr_t)ws) & 255)) return fail(POT_ERR_WORKSPACE, "workspace");
+        std::vector<char> desc(warm_desc_bytes() * batch);
+        for (int k = 0; k < batch; ++k) {
+            const pot_warm_instance& w = inst[k];
+            if (w.n < 1 || w.m < 1) return fail(POT_ERR_INVALID_ARG, "n, m >= 1");
+            if (!w.x || !w.y || !w.r || !w.c || !w.u0 || !w.v0) return fail(POT_ERR_INVALID_ARG, "null pointer");
+            if (!(w.cost_scale > 0.0) || !std::isfinite(w.cost_scale)) return fail(POT_ERR_INVALID_ARG, "cost_scale > 0");
+            double gam = w.gamma;
+            if (!(gam > 0.0)) {
+                const int N = std::max(w.n, w.m);
+                if (N < 2 || !(eps > 0.0)) return fail(POT_ERR_INVALID_ARG, "gamma or eps (with max(n, m) >= 2)");
+                gam = eps / (4.0 * std::log((double)N));
+            }
+            warm_fill_desc(desc.data() + warm_desc_bytes() * k, w.x, w.y, w.r, w.c, w.u0, w.v0, w.cost_scale,
+                           1.0 / gam, w.n, w.m);
+        }
+        hipStream_t st = (hipStream_t)stream;
+        char* base = (char*)ws;
+        float* ctx = (float*)(base + al256((int64_t)warm_desc_bytes() * batch));
+        HIPCHK(hipMemcpyAsync(base, desc.data(), desc.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_warm((const WDesc*)base, batch, weights, ctx, st));
         return POT_OK;
     } catch (...) {
         return fail(POT_ERR_DEVICE, "internal error");

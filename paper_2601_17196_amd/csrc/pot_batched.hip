@@ -50,6 +50,7 @@ struct BShared {
     double a[kBMax];         // offsets of the member's rows (log2 units)
     double b[kBMax];         // column offsets (log2 units)
     double R[kBMax];         // row sums of the member's rows (FP64)
+    double lR[kBMax];        // their logs (start pass only; exact even where R underflows)
     double Q[kBMax];         // column sums (FP64)
     double colw[kBWaves][kBMax];   // per-wave column partials
     double red[64];
@@ -328,6 +329,8 @@ __device__ bool member_pass(Member& M, BShared& S) {
     }
     __syncthreads();
     if (tid == 0) S.K = K;
+    if (PH == PH_INIT)
+        for (int r = tid; r < nr; r += kBThreads) S.lR[r] = log(S.R[r]) + (double)K * kLn2;
     if (ROWS)
         for (int r = tid; r < nr; r += kBThreads) S.R[r] *= scale_d;
     if (COLS) {
@@ -671,16 +674,53 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
     }
     __syncthreads();
 
-    const int valid = member_setup<KIND>(M, S, B);
+    int valid = member_setup<KIND>(M, S, B);
     bool ok = true;
+    // a second attempt runs only as the cold fallback of a warm start (below)
+    for (int attempt = 0; attempt < 2; ++attempt) {
+    const bool cold_retry = attempt > 0;
     if (valid == 0) {
         if (B.algo == POT_ASPOT) {
-            const bool warm = D->u0 || D->v0;
-            if (warm && B.warm_check) {
-                // keep the warm start only if phi(z0) < phi(0); otherwise start cold
+            const bool warm = (D->u0 || D->v0) && !cold_retry;
+            // A warm start (u0, v0, w0) is first made safe by one exact u-block
+            // step (Algorithm 1): u <- u0 + log r~ - log(R + e^u0).  Afterwards
+            // every row sum is at most r~_i and every column sum and the total at
+            // most |r~|_1, whatever the error of the prediction, so the first
+            // momentum step stays in range as from the cold start.  Then one
+            // exact w-block step (w <- w + log s - log T, so that T = s; phi
+            // drops by T - s - s log(s / T)).  A start whose sums are not
+            // representable counts as worse than the cold start.
+            auto warm_init = [&]() __attribute__((always_inline)) -> double {
+                __syncthreads();
+                if (tid == 0) {
+                    A.u0 = D->u0;
+                    A.v0 = D->v0;
+                    A.w0 = D->w0;
+                }
+                __syncthreads();
                 ok = member_pass<KIND, KC, PH_INIT>(M, S);
-                // (a warm start whose sums are not representable counts as worse)
-                const double phi_w = S.ctl.done ? INFINITY : S.ctl.phichk;
+                if (!ok || S.ctl.done) return INFINITY;
+                for (int r = tid; r < M.nr; r += kBThreads) {
+                    const int i = M.r0 + r;
+                    const double u = D->u0 ? D->u0[i] : 0.0;
+                    w.du[i] = u + w.lrt[i] - logaddexp(S.lR[r], u);      // log(R + e^u) in the log domain
+                }
+                __syncthreads();
+                if (tid == 0) A.u0 = w.du;
+                __syncthreads();
+                ok = member_pass<KIND, KC, PH_INIT>(M, S);
+                if (tid == 0 && !S.ctl.done) {
+                    Ctl& c = S.ctl;
+                    const double dw = c.log_s - log(c.T);
+                    c.phichk = c.phichk - c.T + c.s - dw * c.s;
+                    c.wchk[0] += dw;
+                    c.wtil[0] += dw;
+                    c.T = c.s;
+                }
+                __syncthreads();
+                return S.ctl.done ? INFINITY : S.ctl.phichk;
+            };
+            auto cold_init = [&]() __attribute__((always_inline)) -> double {
                 __syncthreads();
                 if (tid == 0) {
                     A.u0 = nullptr;
@@ -691,23 +731,26 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
                     S.ctl.nonfinite = 0;
                 }
                 __syncthreads();
-                if (ok) ok = member_pass<KIND, KC, PH_INIT>(M, S);
-                const double phi_0 = S.ctl.phichk;
-                if (ok && phi_w < phi_0 && !S.ctl.done) {
-                    __syncthreads();
-                    if (tid == 0) {
-                        A.u0 = D->u0;
-                        A.v0 = D->v0;
-                        A.w0 = D->w0;
-                        S.used_warm = 1;
-                    }
-                    __syncthreads();
-                    ok = member_pass<KIND, KC, PH_INIT>(M, S);
+                ok = member_pass<KIND, KC, PH_INIT>(M, S);
+                return S.ctl.phichk;
+            };
+            if (warm && B.warm_check) {
+                // keep the warm start only if phi(z0) < phi(0): cold point first,
+                // then the warm one, which stays unless it is not better
+                const double phi_0 = cold_init();
+                const double phi_w = ok ? warm_init() : INFINITY;
+                if (ok && phi_w < phi_0) {
+                    if (tid == 0) S.used_warm = 1;
+                } else if (ok) {
+                    cold_init();
                 }
+            } else if (warm) {
+                if (tid == 0) S.used_warm = 1;
+                warm_init();
             } else {
-                if (tid == 0) S.used_warm = warm ? 1 : 0;
                 ok = member_pass<KIND, KC, PH_INIT>(M, S);
             }
+            __syncthreads();
             while (ok && !S.ctl.done) {
                 ok = member_pass<KIND, KC, PH_BAR>(M, S);
                 if (!ok || S.ctl.done) break;
@@ -722,23 +765,42 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
                 ok = member_pass<KIND, KC, PH_SK_COL>(M, S);
             }
         }
+        // cold-start ASPOT is the fallback of a warm start whose run left the
+        // representable range (every member takes the same decision)
+        if (B.algo == POT_ASPOT && ok && S.used_warm && S.ctl.status == POT_ERR_NUMERIC && !cold_retry) {
+            __syncthreads();
+            valid = member_setup<KIND>(M, S, B);
+            if (tid == 0) {
+                S.used_warm = 0;
+                A.u0 = nullptr;
+                A.v0 = nullptr;
+                A.w0 = 0.0;
+            }
+            __syncthreads();
+            continue;
+        }
         // form primal: f = u + w (ASPOT) or a (Sinkhorn); g = v or b
         if (ok) {
             const Ctl& c = S.ctl;
             for (int r = tid; r < M.nr; r += kBThreads) {
                 const int i = M.r0 + r;
-                const double f = B.algo == POT_ASPOT ? w.uz[i] + c.wz : (c.out_par ? w.uchk1 : w.uchk0)[i];
+                const double u = B.algo == POT_ASPOT ? w.uz[i] : (c.out_par ? w.uchk1 : w.uchk0)[i];
+                const double f = B.algo == POT_ASPOT ? u + c.wz : u;
                 w.ubar[i] = f;
                 if (D->f_out) D->f_out[i] = f;
+                if (D->u_out) D->u_out[i] = u;
             }
             for (int j = tid; j < m; j += kBThreads) {
                 const double g = w.vz[j];
                 w.vbar[j] = g;
                 if (mem == 0 && D->g_out) D->g_out[j] = g;
+                if (mem == 0 && D->v_out) D->v_out[j] = g;
             }
             __syncthreads();
             if (S.ctl.status != POT_ERR_NUMERIC && B.do_round) ok = member_round<KIND>(M, S);
         }
+    }
+    break;
     }
     if (mem == 0 && tid == 0) {
         const Ctl& c = S.ctl;
@@ -758,6 +820,7 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
         R.T2 = c.T2;
         R.cost_scale = 1.0;
         R.cmax = c.cmax;
+        R.w = B.algo == POT_ASPOT ? c.wz : 0.0;
     }
     __syncthreads();
 }

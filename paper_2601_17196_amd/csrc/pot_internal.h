@@ -122,6 +122,8 @@ struct BDesc {
     const double* v0;                 // warm start (m), or NULL
     double* f_out;                    // log scalings out (n), or NULL
     double* g_out;                    // (m), or NULL
+    double* u_out;                    // duals out (n), or NULL
+    double* v_out;                    // (m), or NULL
     double s, cmax, w0;
     int32_t n, m, G, vec;             // vec: 16-byte vector loads of C allowed
     int64_t off;                      // byte offset of the instance's region in the workspace
@@ -162,5 +164,17 @@ __host__ __device__ inline BLayout blayout(int n, int m, int G) {
     L.total = L.rowsc + al(8 * (int64_t)kScal * G);
     return L;
 }
+
+// one instance of the warm-start inference (pot_warm_predict)
+struct WDesc {
+    const float* x;
+    const float* y;
+    const double* r;
+    const double* c;
+    double* u0;
+    double* v0;
+    double cost_scale, inv_gamma;
+    int32_t n, m;
+};
 
 }  // namespace pot

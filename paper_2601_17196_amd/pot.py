@@ -53,6 +53,16 @@ class Options(ct.Structure):
                 ("member_elems", ct.c_int32)]
 
 
+class BatchOutputs(ct.Structure):
+    _fields_ = [("f", ct.c_void_p), ("g", ct.c_void_p), ("u", ct.c_void_p), ("v", ct.c_void_p)]
+
+
+class WarmInstance(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("m", ct.c_int32), ("x", ct.c_void_p), ("y", ct.c_void_p),
+                ("r", ct.c_void_p), ("c", ct.c_void_p), ("cost_scale", ct.c_double), ("gamma", ct.c_double),
+                ("u0", ct.c_void_p), ("v0", ct.c_void_p)]
+
+
 class Warm(ct.Structure):
     _fields_ = [("u0", ct.c_void_p), ("v0", ct.c_void_p), ("w0", ct.c_void_p), ("check", ct.c_int32)]
 
@@ -62,7 +72,7 @@ class Result(ct.Structure):
                 ("used_warm", ct.c_int32), ("cost", ct.c_double), ("E", ct.c_double),
                 ("gamma", ct.c_double), ("tol", ct.c_double), ("phi", ct.c_double),
                 ("mass", ct.c_double), ("kappa", ct.c_double), ("lambda_", ct.c_double),
-                ("T2", ct.c_double), ("cost_scale", ct.c_double), ("cmax", ct.c_double)]
+                ("T2", ct.c_double), ("cost_scale", ct.c_double), ("cmax", ct.c_double), ("w", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -98,9 +108,14 @@ def load():
                               ct.POINTER(Result), ct.POINTER(Outputs), ct.c_void_p]
     lib.pot_solve.restype = ct.c_int
     lib.pot_solve_batched.argtypes = [ct.c_int32, ct.POINTER(Problem), ct.POINTER(Options), ct.POINTER(Warm),
-                                      ct.c_void_p, ct.c_size_t, ct.POINTER(Result), ct.POINTER(ct.c_void_p),
-                                      ct.POINTER(ct.c_void_p), ct.c_void_p]
+                                      ct.c_void_p, ct.c_size_t, ct.POINTER(Result), ct.POINTER(BatchOutputs),
+                                      ct.c_void_p]
     lib.pot_solve_batched.restype = ct.c_int
+    lib.pot_warm_workspace_bytes.argtypes = [ct.c_int32]
+    lib.pot_warm_workspace_bytes.restype = ct.c_size_t
+    lib.pot_warm_predict.argtypes = [ct.c_int32, ct.POINTER(WarmInstance), ct.c_double, ct.c_void_p, ct.c_void_p,
+                                     ct.c_size_t, ct.c_void_p]
+    lib.pot_warm_predict.restype = ct.c_int
     lib.pot_time_pass.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
                                   ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.c_void_p]
     lib.pot_time_pass.restype = ct.c_int
@@ -273,12 +288,13 @@ def workspace_bytes_batched(problems, opts=None) -> int:
 
 
 def solve_batched(problems, eps, algo=ASPOT, u0=None, v0=None, w0=None, warm_check=True, want_duals=True,
-                  stream=None, workspace=None, raise_on_error=False, **opt_kw):
+                  want_uv=False, stream=None, workspace=None, raise_on_error=False, **opt_kw):
     """Solve a list of instances through pot_solve_batched (one persistent
     launch).  problems: list of dicts with keys r, c, s, C (device tensors;
     optional ldc, kind, cmax).  u0 / v0: optional lists of device FP64
     tensors (entries may be None), w0: optional list of floats.
-    Returns (status, list of result dicts, list of (f, g) tensors or None)."""
+    Returns (status, list of result dicts, list of (f, g) tensors or None);
+    with want_uv the third item holds (f, g, u, v) tuples."""
     import torch
     lib = load()
     B = len(problems)
@@ -293,16 +309,27 @@ def solve_batched(problems, eps, algo=ASPOT, u0=None, v0=None, w0=None, warm_che
     base = workspace.data_ptr()
     aligned = (base + 255) & ~255
     avail = workspace.numel() - (aligned - base)
-    fg = None
-    fp = gp = None
-    if want_duals:
-        fs = [torch.empty(p["r"].shape[0], dtype=torch.float64, device=dev) for p in problems]
-        gs = [torch.empty(p["c"].shape[0], dtype=torch.float64, device=dev) for p in problems]
-        fp = (ct.c_void_p * B)(*[t.data_ptr() for t in fs])
-        gp = (ct.c_void_p * B)(*[t.data_ptr() for t in gs])
-        fg = list(zip(fs, gs))
-    warm = None
     keep = []
+    outs = None
+    bo = None
+    if want_duals or want_uv:
+        f64 = dict(dtype=torch.float64, device=dev)
+        fs = [torch.empty(p["r"].shape[0], **f64) for p in problems]
+        gs = [torch.empty(p["c"].shape[0], **f64) for p in problems]
+        bo = BatchOutputs()
+
+        def arr(ts):
+            a = (ct.c_void_p * B)(*[t.data_ptr() for t in ts])
+            keep.append(a)
+            return ct.cast(a, ct.c_void_p)
+        bo.f, bo.g = arr(fs), arr(gs)
+        outs = list(zip(fs, gs))
+        if want_uv:
+            us = [torch.empty(p["r"].shape[0], **f64) for p in problems]
+            vs = [torch.empty(p["c"].shape[0], **f64) for p in problems]
+            bo.u, bo.v = arr(us), arr(vs)
+            outs = list(zip(fs, gs, us, vs))
+    warm = None
     if u0 is not None or v0 is not None:
         warm = Warm()
         if u0 is not None:
@@ -320,10 +347,55 @@ def solve_batched(problems, eps, algo=ASPOT, u0=None, v0=None, w0=None, warm_che
         warm.check = 1 if warm_check else 0
     res = (Result * B)()
     st = lib.pot_solve_batched(B, probs, ct.byref(opts), ct.byref(warm) if warm is not None else None,
-                               ct.c_void_p(aligned), ct.c_size_t(avail), res, fp, gp, _stream_ptr(stream))
+                               ct.c_void_p(aligned), ct.c_size_t(avail), res,
+                               ct.byref(bo) if bo is not None else None, _stream_ptr(stream))
     if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
         raise PotError(st, last_error())
-    return int(st), [res[k].as_dict() for k in range(B)], fg
+    return int(st), [res[k].as_dict() for k in range(B)], outs
+
+
+def warm_blob(arrays=None, device="cuda"):
+    """Device weight blob of the warm-start network (uint8 tensor); arrays:
+    dict of FP32/FP64 numpy weights (default: the trained weights shipped
+    with the package)."""
+    import torch
+
+    from . import warmstart as W
+    arr = arrays if arrays is not None else W.load_arrays()
+    return torch.from_numpy(W.pack_blob(arr)).to(device)
+
+
+def warm_predict(instances, eps, blob, stream=None, workspace=None):
+    """Warm starts (u0, v0) for a list of dicts with keys x, y (n x 2 and
+    m x 2 float32), r, c (float64), cost_scale and optional gamma (device
+    tensors).  Runs the inference kernels; returns a list of (u0, v0)."""
+    import torch
+    lib = load()
+    B = len(instances)
+    arr = (WarmInstance * B)()
+    outs = []
+    dev = instances[0]["r"].device
+    for k, d in enumerate(instances):
+        n, m = int(d["x"].shape[0]), int(d["y"].shape[0])
+        u0 = torch.empty(n, dtype=torch.float64, device=dev)
+        v0 = torch.empty(m, dtype=torch.float64, device=dev)
+        w = arr[k]
+        w.n, w.m = n, m
+        w.x, w.y, w.r, w.c = _ptr(d["x"]), _ptr(d["y"]), _ptr(d["r"]), _ptr(d["c"])
+        w.cost_scale = float(d["cost_scale"])
+        w.gamma = float(d.get("gamma", 0.0))
+        w.u0, w.v0 = _ptr(u0), _ptr(v0)
+        outs.append((u0, v0))
+    nbytes = int(lib.pot_warm_workspace_bytes(B))
+    if workspace is None or workspace.numel() < nbytes + 256:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) & ~255
+    st = lib.pot_warm_predict(B, arr, float(eps), ct.c_void_p(blob.data_ptr()), ct.c_void_p(aligned),
+                              ct.c_size_t(workspace.numel() - (aligned - base)), _stream_ptr(stream))
+    if st != OK:
+        raise PotError(st, last_error())
+    return outs
 
 
 def to_device_instance(inst, device="cuda", kind="f32", pad_ldc=False):

@@ -1,0 +1,112 @@
+"""Turn rocprofv3 CSV output into the short summaries kept under profiles/.
+
+  python -m paper_2601_17196_amd.profile_summary stats KERNEL_STATS_CSV --title T --command C --out FILE.md
+  python -m paper_2601_17196_amd.profile_summary pmc FETCH_CSV WRITE_CSV --out FILE.json --command C ...
+
+The pmc mode reads two counter-collection runs (FETCH_SIZE, then WRITE_SIZE,
+KiB per dispatch), averages them per kernel, and scales them by the factor
+that makes a plain device copy of known size read and write exactly its
+bytes.  It records a hash of the kernel sources, so that a consumer can tell
+whether the counters still describe the current kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/pot_kernels.hip", "csrc/pot_device.h", "csrc/pot_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats_table(path, title, command):
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# {title}", "", "Command (repository root, one MI355X):", "", "    export TMPDIR=/tmp"]
+    out += ["    " + line for line in command.split("\n")]
+    out += ["", "| kernel | calls | total ms | average us | min us | max us |", "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| `{r['Name'][:72]}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def per_kernel(path, counter):
+    """{kernel name: [value per dispatch]} for one counter (values summed over
+    the rows of a dispatch)."""
+    acc = collections.defaultdict(float)
+    name = {}
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = r["Dispatch_Id"]
+        acc[key] += float(r["Counter_Value"])
+        name[key] = r["Kernel_Name"]
+    out = collections.defaultdict(list)
+    for key, v in acc.items():
+        out[name[key]].append(v)
+    return out
+
+
+def pmc_summary(fetch_csv, write_csv, copy_bytes, copy_pattern, kernel_pattern, command):
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+
+    def pick(d, pat):
+        vals = [v for k, lst in d.items() if pat in k for v in lst]
+        return sum(vals) / len(vals) if vals else None, len(vals)
+    cf, _ = pick(f, copy_pattern)
+    cw, _ = pick(w, copy_pattern)
+    kf, nf = pick(f, kernel_pattern)
+    kw, nw = pick(w, kernel_pattern)
+    sf = copy_bytes / (cf * 1024.0) if cf else None
+    sw = copy_bytes / (cw * 1024.0) if cw else None
+    out = {"kernel": kernel_pattern, "dispatches": [nf, nw],
+           "fetch_kib_raw": kf, "write_kib_raw": kw,
+           "copy_bytes": copy_bytes, "copy_fetch_kib_raw": cf, "copy_write_kib_raw": cw,
+           "scale_fetch": sf, "scale_write": sw,
+           "fetch_bytes": kf * 1024.0 * sf if kf and sf else None,
+           "write_bytes": kw * 1024.0 * sw if kw and sw else None,
+           "kernel_source_hash": kernel_source_hash(), "command": command}
+    if out["fetch_bytes"] is not None and out["write_bytes"] is not None:
+        out["traffic_bytes"] = out["fetch_bytes"] + out["write_bytes"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--out", required=True)
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_csv")
+    p.add_argument("write_csv")
+    p.add_argument("--copy-bytes", type=float, required=True)
+    p.add_argument("--copy-pattern", default="copy")
+    p.add_argument("--kernel-pattern", required=True)
+    p.add_argument("--command", required=True)
+    p.add_argument("--out", required=True)
+    a = ap.parse_args()
+    if a.mode == "stats":
+        open(a.out, "w").write(stats_table(a.csv, a.title, a.command))
+    else:
+        res = pmc_summary(a.fetch_csv, a.write_csv, a.copy_bytes, a.copy_pattern, a.kernel_pattern, a.command)
+        json.dump(res, open(a.out, "w"), indent=1)
+    print(open(a.out).read())
+
+
+if __name__ == "__main__":
+    main()
