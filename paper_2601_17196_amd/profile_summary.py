@@ -62,11 +62,13 @@ def pmc_summary(fetch_csv, write_csv, copy_bytes, copy_pattern, kernel_pattern, 
     f = per_kernel(fetch_csv, "FETCH_SIZE")
     w = per_kernel(write_csv, "WRITE_SIZE")
 
-    def pick(d, pat):
-        vals = [v for k, lst in d.items() if pat in k for v in lst]
+    def pick(d, pat, floor_kib=0.0):
+        vals = [v for k, lst in d.items() if pat in k for v in lst if v >= floor_kib]
         return sum(vals) / len(vals) if vals else None, len(vals)
-    cf, _ = pick(f, copy_pattern)
-    cw, _ = pick(w, copy_pattern)
+    # copy dispatches of the known size only (uploads of the workload also copy)
+    floor = 0.5 * copy_bytes / 1024.0
+    cf, _ = pick(f, copy_pattern, floor)
+    cw, _ = pick(w, copy_pattern, floor)
     kf, nf = pick(f, kernel_pattern)
     kw, nw = pick(w, kernel_pattern)
     sf = copy_bytes / (cf * 1024.0) if cf else None
