@@ -1,0 +1,88 @@
+"""The full-size single instance (n = m = 20000, 2-D shifted mixtures,
+s = 0.7, eps = 1e-2) through pot_solve, FP32 and BF16 costs.
+
+The oracle cannot solve this size, so the checks are those that hold at any
+size or that the oracle computes one output at a time:
+  * the solve stops at E <= eps~ and the rounded plan carries mass s;
+  * row and column feasibility of the rounded plan from its factors
+    (X = kappa diag(alpha) X~ diag(beta) + lambda p' q'^T);
+  * alpha_i = min(1, r_i / (X~ 1)_i) on sampled rows, recomputed in FP64 on the
+    host from the returned duals over all 20000 columns;
+  * the BF16-cost solve is within eps of the FP32 one (both eps-approximate)."""
+import numpy as np
+import pytest
+
+from paper_2601_17196_amd import instances as I
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _device_cost(inst, dtype):
+    """C = cost_scale |x_i - y_j|^2 in FP64 on the device (the generator's
+    formula, coordinate by coordinate), stored as FP32 or BF16 bits."""
+    import torch
+    x = torch.from_numpy(inst.x.astype(np.float64)).cuda()
+    y = torch.from_numpy(inst.y.astype(np.float64)).cuda()
+    C = torch.empty((inst.n, inst.m), dtype=torch.float32 if dtype == "f32" else torch.bfloat16, device="cuda")
+    for i0 in range(0, inst.n, 2048):
+        xb = x[i0:i0 + 2048]
+        D = torch.zeros((xb.shape[0], inst.m), dtype=torch.float64, device="cuda")
+        for k in range(x.shape[1]):
+            diff = xb[:, k:k + 1] - y[None, :, k]
+            D += diff * diff
+        C[i0:i0 + 2048] = (D * inst.cost_scale).to(C.dtype)
+    return C if dtype == "f32" else C.view(torch.int16)
+
+
+def test_full_size_instance():
+    import torch
+
+    from paper_2601_17196_amd import pot
+    inst = I.c3(0, dense=False)
+    print(f"full size: n = m = {inst.n}", flush=True)
+    r = torch.from_numpy(inst.r).cuda()
+    c = torch.from_numpy(inst.c).cuda()
+    C32 = _device_cost(inst, "f32")
+    # the device cost agrees with the generator's FP64 arithmetic on sampled rows
+    g = np.random.default_rng(0)
+    rows = g.choice(inst.n, 6, replace=False)
+    X = inst.x.astype(np.float64)
+    Y = inst.y.astype(np.float64)
+    Crow = {}
+    for i in rows:
+        d = np.zeros(inst.m)
+        for k in range(2):
+            diff = X[i, k] - Y[:, k]
+            d += diff * diff
+        Crow[i] = (d * inst.cost_scale).astype(np.float32)
+        assert np.array_equal(C32[i].cpu().numpy(), Crow[i])
+    out = pot.solve(r, c, inst.s, inst.eps, C=C32, cmax=0.0)
+    torch.cuda.synchronize()
+    res = out.result
+    print(f"FP32: status {out.status} iters {res['iters']} cost {res['cost']:.9e} E {res['E']:.3e}", flush=True)
+    assert out.status == 0 and res["E"] <= res["tol"]
+    assert abs(res["mass"] - inst.s) <= 1e-11
+    # feasibility from the factors
+    kap, lam = res["kappa"], res["lambda_"]
+    pp, qq = out.pp.cpu().numpy(), out.qq.cpu().numpy()
+    rows_sum = kap * (inst.r - pp) + lam * pp * qq.sum()
+    cols_sum = kap * (inst.c - qq) + lam * qq * pp.sum()
+    assert np.all(pp >= 0) and np.all(qq >= 0)
+    assert np.all(rows_sum <= inst.r * (1 + 1e-12) + 1e-300)
+    assert np.all(cols_sum <= inst.c * (1 + 1e-12) + 1e-300)
+    # alpha on sampled rows from the duals (FP64, host)
+    f, gg, alpha = out.f.cpu().numpy(), out.g.cpu().numpy(), out.alpha.cpu().numpy()
+    gam = res["gamma"]
+    for i in rows:
+        Ri = float(np.sum(np.exp(f[i] + gg - Crow[i].astype(np.float64) / gam)))
+        a = min(1.0, inst.r[i] / Ri) if Ri > 0 else 1.0
+        assert abs(alpha[i] - a) <= 1e-12 * max(a, 1e-300), (i, alpha[i], a)
+    del C32
+    torch.cuda.empty_cache()
+    Cb = _device_cost(inst, "bf16")
+    ob = pot.solve(r, c, inst.s, inst.eps, C=Cb, kind=pot.COST_BF16, ldc=inst.m, cmax=0.0)
+    torch.cuda.synchronize()
+    print(f"BF16: status {ob.status} iters {ob.result['iters']} cost {ob.result['cost']:.9e}", flush=True)
+    assert ob.status == 0 and ob.result["E"] <= ob.result["tol"]
+    assert abs(ob.result["mass"] - inst.s) <= 1e-11
+    assert abs(ob.result["cost"] - res["cost"]) <= inst.eps
