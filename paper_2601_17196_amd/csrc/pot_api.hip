@@ -56,14 +56,11 @@ static Geometry geometry(const pot_problem* p, const pot_options* o) {
     g.bc = 64 * vec_width(p->kind);
     int br = (o && o->tile_rows > 0) ? o->tile_rows : 0;
     if (br == 0) {
-        // default: the tallest tile (fewer row partials, a longer sweep per
-        // workgroup) that still gives at least 2 workgroups per CU (512 on
-        // 256 CUs); measured best on 4096 x 4096 for FP32 (128 rows) and
-        // BF16 (64 rows)
+        // default: 128-row tiles when they give at least 2 workgroups per CU
+        // (512 on 256 CUs), else 64; measured best on 4096 x 4096 (FP32: 128,
+        // BF16: 64) and on 20000 x 20000 (128 beats 256 and 64)
         const int nx = (p->m + g.bc - 1) / g.bc;
-        br = 64;
-        for (int cand : {256, 128})
-            if ((int64_t)nx * ((p->n + cand - 1) / cand) >= 512) { br = cand; break; }
+        br = (int64_t)nx * ((p->n + 127) / 128) >= 512 ? 128 : 64;
     }
     br = std::max(4, std::min(br, 256));
     g.br = br;

@@ -122,6 +122,15 @@ __device__ void sk_col_finalise(const PassArgs& A, const Ctl& c, int j0, int col
     }
 }
 
+// Tile of this workgroup.  Tiles are numbered along rows (column index
+// fastest).  The launch deals workgroups to the 8 XCDs round robin, so the
+// first 8 floor(T / 8) workgroups are renumbered to give each XCD a
+// contiguous run of tiles: the XCDs stream disjoint bands of whole rows.
+__device__ __forceinline__ int tile_index() {
+    const unsigned b = blockIdx.x, q = gridDim.x / 8u;
+    return (int)(b < 8u * q ? (b % 8u) * q + b / 8u : b);
+}
+
 // ---------------------------------------------------------------------------
 // the statistics pass
 // ---------------------------------------------------------------------------
@@ -150,8 +159,8 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     double* s_col = s_buf;                 // [4][bc]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = blockIdx.x;
-    const int ty = tile % A.ny, tx = tile / A.ny;
+    const int tile = tile_index();
+    const int tx = tile % A.nx, ty = tile / A.nx;
     const int i0 = ty * A.br, j0 = tx * A.bc;
     const int rows = min(A.br, A.n - i0), cols = min(A.bc, A.m - j0);
     const int jg = j0 + lane * VW;         // this lane's first column
@@ -532,7 +541,7 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
     __syncthreads();
     if (s_last) {
         decide(A, s_ctl, s_red);
-        if (tid == 0) A.ws.glob[0] = 0;
+        if (tid == 0) st_agent(&A.ws.glob[0], 0);
     }
 }
 
@@ -559,7 +568,8 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
     __shared__ int s_flags[4];
     Ctl& c = *A.ws.ctl;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ty = blockIdx.x % A.ny, tx = blockIdx.x / A.ny;
+    const int tile = tile_index();
+    const int tx = tile % A.nx, ty = tile / A.nx;
     const int i0 = ty * A.br, j0 = tx * A.bc;
     const int rows = min(A.br, A.n - i0), cols = min(A.bc, A.m - j0);
     const Ws& w = A.ws;
@@ -656,7 +666,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
         block_sum<kScal>(acc, s_red);
         if (tid == 0) {
             for (int k = 0; k < kScal; ++k) st_agent(&w.rowscal[(int64_t)ty * kScal + k], acc[k]);
-            w.rowcnt[ty] = 0;
+            st_agent(&w.rowcnt[ty], 0);        // (atomic, like the increments)
         }
         ++nfin;
     }
@@ -679,7 +689,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
         block_sum<kScal>(acc, s_red);
         if (tid == 0) {
             for (int k = 0; k < kScal; ++k) st_agent(&w.colscal[(int64_t)tx * kScal + k], acc[k]);
-            w.colcnt[tx] = 0;
+            st_agent(&w.colcnt[tx], 0);
         }
         ++nfin;
     }
@@ -711,7 +721,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
                     c.cost = c.kappa * c.cost1 + c.lambda * c.pcq;
                     c.mass = c.kappa * T2 + c.lambda * c.np * c.nq;
                 }
-                w.glob[0] = 0;
+                st_agent(&w.glob[0], 0);
             }
         }
     }
