@@ -60,10 +60,10 @@ def run_solve(pot, d, eps, algo, kind, **kw):
                      algo=algo, **kw)
 
 
-def time_solves(pot, d, eps, algo, kind, steps, warmup, workspace):
+def time_solves(pot, d, eps, algo, kind, steps, warmup, workspace, **kw):
     import torch
     for _ in range(warmup):
-        run_solve(pot, d, eps, algo, kind, workspace=workspace, want_factors=False)
+        run_solve(pot, d, eps, algo, kind, workspace=workspace, want_factors=False, **kw)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -71,7 +71,7 @@ def time_solves(pot, d, eps, algo, kind, steps, warmup, workspace):
     e0.record()
     outs = []
     for _ in range(steps):
-        outs.append(run_solve(pot, d, eps, algo, kind, workspace=workspace, want_factors=False))
+        outs.append(run_solve(pot, d, eps, algo, kind, workspace=workspace, want_factors=False, **kw))
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -304,6 +304,17 @@ def main():
             log(f"{name}: {extra[name]}")
             del d2
             torch.cuda.empty_cache()
+        # the tuned rule of Algorithm 3 (Theorem 2) on the same instance; its
+        # cost is compared with the ASPOT cost (within eps of the optimum)
+        if args.kind == "f32":
+            for p in (2.0, 3.0):
+                name = f"sinkhorn_tuned_p{int(p)}"
+                o2, w2, ev2 = time_solves(pot, d, eps, pot.SINKHORN, "f32", 3, 1, None, gamma_rule=1, p=p)
+                rr = o2[-1].result
+                extra[name] = {"solves_per_s": 3 / (ev2 / 1e3), "iters": rr["iters"], "cost": rr["cost"],
+                               "gamma": rr["gamma"], "tol": rr["tol"],
+                               "cost_minus_aspot": rr["cost"] - outs[-1].result["cost"] if algo == pot.ASPOT else None}
+                log(f"{name}: {extra[name]}")
 
     if not args.no_batched:
         log("batched: 512 uneven instances")

@@ -114,6 +114,12 @@ typedef struct {
     int32_t member_elems;  /* pot_solve_batched: an instance with more than this many cost entries is
                               split by rows over a group of workgroups, each sweeping at most this
                               many (0: autotuned on the batch, cached per batch shape) */
+    int32_t gamma_rule;    /* 0: gamma and tol as above.  1 (algo Sinkhorn only): the tuned rule of
+                              Algorithm 3 (Theorem 2), gamma = (2 eps / (49 H_min))^(1/p) and
+                              tol = H_min gamma^p with H_min = min(H(r), H(c)),
+                              H(x) = -sum_i x_i ln x_i (0 ln 0 = 0), over the masses as given; a
+                              positive gamma or tol above still overrides.  Needs H_min > 0 */
+    double p;              /* exponent of the tuned rule, finite and >= 1 */
 } pot_options;
 
 typedef struct {

@@ -146,6 +146,31 @@ int potref_setup(int n, int m, const double* r, const double* c, double s,
     return POTREF_OK;
 }
 
+/* Tuned rule of Algorithm 3 (statement of Theorem 2): with the Shannon
+   entropy H(x) = -sum_i x_i log x_i of each marginal as given (terms with
+   x_i = 0 contribute 0), H_min = min{H(r), H(c)}, gamma = (2 eps /
+   (49 H_min))^(1/p) and the stopping threshold eps' = H_min gamma^p.
+   out3 = {gamma, eps', H_min}. */
+int potref_tuned(int n, int m, const double* r, const double* c, double eps, double p, double* out3) {
+    if (n < 1 || m < 1 || !(eps > 0.0) || !(p >= 1.0) || !isfinite(p)) return POTREF_INVALID;
+    double hr = 0.0, hc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(r[i] >= 0.0) || !isfinite(r[i])) return POTREF_INVALID;
+        if (r[i] > 0.0) hr -= r[i] * log(r[i]);
+    }
+    for (int j = 0; j < m; ++j) {
+        if (!(c[j] >= 0.0) || !isfinite(c[j])) return POTREF_INVALID;
+        if (c[j] > 0.0) hc -= c[j] * log(c[j]);
+    }
+    double h = hr < hc ? hr : hc;
+    if (!(h > 0.0)) return POTREF_INVALID;
+    double gamma = pow(2.0 * eps / (49.0 * h), 1.0 / p);
+    out3[0] = gamma;
+    out3[1] = h * pow(gamma, p);
+    out3[2] = h;
+    return POTREF_OK;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Statistics of B(z).                                                     */
 /* ---------------------------------------------------------------------- */

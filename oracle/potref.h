@@ -46,6 +46,12 @@ int potref_setup(int n, int m, const double* r, const double* c, double s,
                  double eps, double cmax, double gamma_user, double tol_user,
                  double* rt, double* ct, double* out3);
 
+/* Tuned rule of Algorithm 3 (Theorem 2): out3 = {gamma, eps', H_min} with
+ * H_min = min{H(r), H(c)}, H(x) = -sum x_i log x_i (0 log 0 = 0),
+ * gamma = (2 eps / (49 H_min))^(1/p), eps' = H_min gamma^p.  Invalid unless
+ * p >= 1 and H_min > 0. */
+int potref_tuned(int n, int m, const double* r, const double* c, double eps, double p, double* out3);
+
 /* Statistics of B(z) in log domain: lR (n), lQ (m), lT (1). */
 void potref_stats(int n, int m, const double* C, long ldc, double gamma,
                   const double* u, const double* v, double w,

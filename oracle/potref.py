@@ -18,6 +18,7 @@ __all__ = [
     "build_oracle",
     "load",
     "setup",
+    "tuned",
     "stats",
     "phi",
     "error",
@@ -80,6 +81,8 @@ def load():
     lib.potref_setup.argtypes = [ct.c_int, ct.c_int, _D, _D, ct.c_double, ct.c_double,
                                  ct.c_double, ct.c_double, ct.c_double, _D, _D, _D]
     lib.potref_setup.restype = ct.c_int
+    lib.potref_tuned.argtypes = [ct.c_int, ct.c_int, _D, _D, ct.c_double, ct.c_double, _D]
+    lib.potref_tuned.restype = ct.c_int
     lib.potref_stats.argtypes = [ct.c_int, ct.c_int, _D, ct.c_long, ct.c_double, _D, _D,
                                  ct.c_double, _D, _D, _D]
     lib.potref_stats.restype = None
@@ -140,6 +143,18 @@ def setup(r, c, s, eps, cmax=1.0, gamma=0.0, tol=0.0):
     if st != 0:
         raise ValueError("invalid POT setup arguments")
     return float(out[0]), float(out[1]), float(out[2]), rt, cc
+
+
+def tuned(r, c, eps, p):
+    """Tuned rule of Algorithm 3 (Theorem 2): returns (gamma, eps', H_min)."""
+    lib = load()
+    r = _f64(r)
+    c = _f64(c)
+    out = np.empty(3)
+    st = lib.potref_tuned(len(r), len(c), _p(r), _p(c), float(eps), float(p), _p(out))
+    if st != 0:
+        raise ValueError("tuned rule needs p >= 1, valid masses and min(H(r), H(c)) > 0")
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def stats(C, gamma, u, v, w):
@@ -304,6 +319,12 @@ def cost(C, X):
     return float(lib.potref_cost(n, m, _p(C), m, _p(X)))
 
 
+def tuned_tol(r, c, gamma, p):
+    """eps' = H_min gamma^p of the tuned rule at a given gamma."""
+    _, _, h = tuned(r, c, 1.0, p)
+    return h * gamma ** p
+
+
 @dataclasses.dataclass
 class OracleSolution:
     algo: str
@@ -322,12 +343,22 @@ class OracleSolution:
 
 
 def solve(C, r, c, s, eps, algo="aspot", cmax=None, gamma=0.0, tol=0.0, max_iter=100000,
-          block_rule=0, step_rule=0, trace=False, A=None, z0=None, dense=False):
+          block_rule=0, step_rule=0, trace=False, A=None, z0=None, dense=False, gamma_rule=0, p=1.0):
     """Setup, solve and round: Algorithm 2 (algo="aspot") or Algorithm 3 with
-    the default gamma and stopping rule (algo="sinkhorn")."""
+    the default gamma and stopping rule (algo="sinkhorn"); gamma_rule=1 takes
+    Algorithm 3's tuned gamma and threshold (Theorem 2) where gamma and tol
+    are not given."""
     C = _f64(C)
     if cmax is None:
         cmax = float(C.max())
+    if gamma_rule == 1:
+        if algo != "sinkhorn":
+            raise ValueError("the tuned rule is Algorithm 3's (Sinkhorn)")
+        tg, tt, _ = tuned(r, c, eps, p)
+        if not gamma > 0.0:
+            gamma = tg
+        if not tol > 0.0:
+            tol = tt if gamma == tg else tuned_tol(r, c, gamma, p)
     gam, tl, M, rt, cc = setup(r, c, s, eps, cmax=cmax, gamma=gamma, tol=tol)
     if algo == "aspot":
         u, v, w, it, E, st, tr = aspot(C, gam, tl, rt, cc, s, M, max_iter=max_iter,

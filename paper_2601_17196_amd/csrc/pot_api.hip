@@ -122,7 +122,12 @@ static pot_status check_problem(const pot_problem* p, const pot_options* o) {
     if (!(o->eps > 0.0) || !std::isfinite(o->eps)) return fail(POT_ERR_INVALID_ARG, "eps must be finite and > 0");
     if (!std::isfinite(o->gamma) || !std::isfinite(o->tol) || !std::isfinite(o->A))
         return fail(POT_ERR_INVALID_ARG, "gamma, tol and A must be finite");
-    if (o->gamma <= 0.0 && std::max(p->n, p->m) < 2)
+    if (o->gamma_rule < 0 || o->gamma_rule > 1) return fail(POT_ERR_INVALID_ARG, "gamma_rule is 0 or 1");
+    if (o->gamma_rule == 1 && o->algo != POT_SINKHORN)
+        return fail(POT_ERR_INVALID_ARG, "gamma_rule 1 (the tuned rule of Algorithm 3) is for algo Sinkhorn");
+    if (o->gamma_rule == 1 && !(o->p >= 1.0 && std::isfinite(o->p)))
+        return fail(POT_ERR_INVALID_ARG, "the tuned rule needs a finite p >= 1");
+    if (o->gamma <= 0.0 && o->gamma_rule == 0 && std::max(p->n, p->m) < 2)
         return fail(POT_ERR_INVALID_ARG, "default gamma needs max(n, m) >= 2 (ln 1 = 0)");
     if (o->algo != POT_ASPOT && o->algo != POT_SINKHORN) return fail(POT_ERR_INVALID_ARG, "unknown algo");
     if (o->block_rule < 0 || o->block_rule > 1) return fail(POT_ERR_INVALID_ARG, "block_rule");
@@ -272,8 +277,9 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     }
 
     // every exponent log2(e) C_ij / gamma must stay below 2^29 (the kernels
-    // split exponents into an int32 part and a fraction)
-    {
+    // split exponents into an int32 part and a fraction; the setup kernel
+    // checks the tuned rule's gamma)
+    if (o->gamma > 0.0 || o->gamma_rule == 0) {
         const int N = std::max(p->n, p->m);
         const double gam = o->gamma > 0.0 ? o->gamma : o->eps / (4.0 * std::log((double)N));
         if (!(1.4426950408889634 * cmax / gam < 536870912.0))
@@ -283,6 +289,7 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     // --- setup (Algorithm 2, "Approximating POT") and validation of r, c, s
     SetupArgs S;
     S.n = p->n; S.m = p->m; S.algo = o->algo; S.nx = g.nx; S.ny = g.ny;
+    S.gamma_rule = o->gamma_rule; S.p = o->p;
     S.s = p->s; S.eps = o->eps; S.gamma_user = o->gamma; S.tol_user = o->tol; S.A_user = o->A;
     S.cmax = cmax; S.cost_scale = cost_scale; S.w0 = o->w0;
     S.r = p->r; S.c = p->c; S.ws = w;
@@ -294,8 +301,10 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
         static const char* why[] = {"", "r or c has a negative or non-finite entry",
                                     "s must satisfy 0 < s <= min(|r|_1, |c|_1)", "gamma is not positive",
                                     "eps~ capped to 0 (s equals a mass above 1) and no tol given",
-                                    "a smoothed marginal is not positive"};
-        return fail(POT_ERR_INVALID_ARG, why[valid < 6 ? valid : 0]);
+                                    "a smoothed marginal is not positive", "",
+                                    "|C|_max / gamma too large (exponents beyond 2^29)",
+                                    "the tuned rule needs min(H(r), H(c)) > 0"};
+        return fail(POT_ERR_INVALID_ARG, why[valid < 9 ? valid : 0]);
     }
 
     PassArgs A;
@@ -520,6 +529,9 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
     if (o->block_rule < 0 || o->block_rule > 1 || o->step_rule < 0 || o->step_rule > 1)
         return fail(POT_ERR_INVALID_ARG, "block_rule and step_rule are 0 or 1");
     if (o->member_elems < 0) return fail(POT_ERR_INVALID_ARG, "member_elems >= 0");
+    if (o->gamma_rule < 0 || o->gamma_rule > 1) return fail(POT_ERR_INVALID_ARG, "gamma_rule is 0 or 1");
+    if (o->gamma_rule == 1 && (o->algo != POT_SINKHORN || !(o->p >= 1.0 && std::isfinite(o->p))))
+        return fail(POT_ERR_INVALID_ARG, "the tuned rule needs algo Sinkhorn and a finite p >= 1");
     if (o->force || o->trace_i || o->trace_d) return fail(POT_ERR_UNSUPPORTED, "force and trace are single-solve options");
     const int kind = probs[0].kind;
     if (kind != POT_COST_F32 && kind != POT_COST_BF16)
@@ -598,6 +610,8 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
     B.do_round = (o->flags & POT_FLAG_NO_ROUND) ? 0 : 1;
     B.eps = o->eps;
     B.gamma_user = o->gamma;
+    B.gamma_rule = o->gamma_rule;
+    B.p = o->p;
     B.tol_user = o->tol;
     B.A_user = o->A;
     const bool use_graph = !(o->flags & POT_FLAG_NO_GRAPH);
@@ -719,6 +733,7 @@ pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void*
         layout(prob, g, (char*)ws, &w);
         SetupArgs S;
         S.n = prob->n; S.m = prob->m; S.algo = POT_ASPOT; S.nx = g.nx; S.ny = g.ny;
+        S.gamma_rule = opts->gamma_rule; S.p = opts->p;
         S.s = prob->s; S.eps = opts->eps; S.gamma_user = opts->gamma; S.tol_user = opts->tol;
         S.A_user = opts->A; S.cmax = prob->cmax;
         S.cost_scale = prob->kind == POT_COST_SQEUCLID_POINTS ? prob->cost_scale : 1.0;

@@ -421,18 +421,20 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = M.n, m = M.m;
     const Ws& w = M.A.ws;
-    double v[3] = {0.0, 0.0, 0.0};      // |r|_1, |c|_1, bad masses
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};      // |r|_1, |c|_1, bad masses, H(r), H(c)
     for (int i = tid; i < n; i += kBThreads) {
         const double x = D.r[i];
         v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
         v[0] += x;
+        v[3] += ent(x);
     }
     for (int j = tid; j < m; j += kBThreads) {
         const double x = D.c[j];
         v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
         v[1] += x;
+        v[4] += ent(x);
     }
-    block_sum<3, kBWaves>(v, S.red);
+    block_sum<5, kBWaves>(v, S.red);
     double cmax = D.cmax;
     int bad_cost = 0;
     if (!(cmax > 0.0)) {
@@ -447,9 +449,10 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
         block_sum<1, kBWaves>(q, S.red);
         bad_cost = q[0] > 0.0 || !(cmax > 0.0);
     }
-    const SetupIn in = {n, m, B.algo, D.s, B.eps, B.gamma_user, B.tol_user, B.A_user, cmax, 1.0, D.w0};
+    const SetupIn in = {n, m, B.algo, B.gamma_rule, B.p, D.s, B.eps, B.gamma_user, B.tol_user, B.A_user, cmax, 1.0,
+                        D.w0};
     double gamma, et, tol;
-    int valid = setup_params(in, v[0], v[1], v[2], gamma, et, tol);
+    int valid = setup_params(in, v[0], v[1], v[2], v[3], v[4], gamma, et, tol);
     if (valid == 0 && bad_cost) valid = 6;
     // every exponent log2(e) C_ij / gamma must stay below 2^29 (exponent split)
     if (valid == 0 && !(kLog2e * cmax / gamma < 536870912.0)) valid = 7;

@@ -561,23 +561,35 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
 // setup of Algorithm 2 ("Approximating POT") from the mass sums
 // ---------------------------------------------------------------------------
 struct SetupIn {
-    int n, m, algo;
-    double s, eps, gamma_user, tol_user, A_user, cmax, cost_scale, w0;
+    int n, m, algo, gamma_rule;
+    double p, s, eps, gamma_user, tol_user, A_user, cmax, cost_scale, w0;
 };
 
+// entropy term of one mass: -x ln x, with 0 ln 0 = 0
+__device__ __forceinline__ double ent(double x) { return x > 0.0 ? -x * log(x) : 0.0; }
+
 // gamma, the smoothing weight eps~ (with its two caps) and the stopping
-// threshold; returns the validity code (0 ok) from the sums of r and c and
-// the count of bad (negative or non-finite) masses
-__device__ inline int setup_params(const SetupIn& S, double sr, double sc, double bad, double& gamma, double& et,
-                                   double& tol) {
+// threshold; returns the validity code (0 ok) from the sums of r and c, the
+// count of bad (negative or non-finite) masses and the entropies
+// H(r) = -sum r_i ln r_i, H(c).  The default rule is Algorithm 2's setup;
+// the tuned rule (Algorithm 3 with Theorem 2) takes
+// gamma = (2 eps / (49 H_min))^(1/p) and the threshold eps' = H_min gamma^p,
+// H_min = min(H(r), H(c)); a gamma or tol given by the user wins either way.
+__device__ inline int setup_params(const SetupIn& S, double sr, double sc, double bad, double hr, double hc,
+                                   double& gamma, double& et, double& tol) {
     const int N = S.n > S.m ? S.n : S.m;
-    gamma = S.gamma_user > 0.0 ? S.gamma_user : S.eps / (4.0 * log((double)N));
+    const double hm = fmin(hr, hc);
+    const bool tuned = S.gamma_rule == 1;
+    if (S.gamma_user > 0.0) gamma = S.gamma_user;
+    else if (tuned) gamma = pow(2.0 * S.eps / (49.0 * hm), 1.0 / S.p);
+    else gamma = S.eps / (4.0 * log((double)N));
     et = S.eps / (8.0 * S.cmax);
     if (sr > 1.0) et = fmin(et, 8.0 * (sr - S.s) / (sr - 1.0));
     if (sc > 1.0) et = fmin(et, 8.0 * (sc - S.s) / (sc - 1.0));
-    tol = S.tol_user > 0.0 ? S.tol_user : et;
+    tol = S.tol_user > 0.0 ? S.tol_user : (tuned ? hm * pow(gamma, S.p) : et);
     if (bad > 0.0) return 1;
     if (!(S.s > 0.0) || S.s > sr || S.s > sc) return 2;
+    if (tuned && !(hm > 0.0 && isfinite(hm))) return 8;
     if (!(gamma > 0.0) || !isfinite(gamma)) return 3;
     if (!(tol > 0.0)) return 4;
     return 0;

@@ -100,6 +100,8 @@ struct PassArgs {
 // Arguments of the setup kernel.
 struct SetupArgs {
     int32_t n, m, algo, nx, ny;
+    int32_t gamma_rule;    // 0 default (Algorithm 2 setup), 1 tuned (Algorithm 3)
+    double p;              // exponent of the tuned rule
     double s, eps, gamma_user, tol_user, A_user, cmax, cost_scale, w0;
     const double* r;
     const double* c;
@@ -145,7 +147,8 @@ struct BArgs {
     int32_t warm_check;               // 1: keep a warm start only if phi(z0) < phi(0)
     int32_t spin_limit;               // bound of every wait of a group barrier
     int32_t do_round;                 // 0: skip the rounding (timing runs of the autotuner)
-    int32_t pad_;
+    int32_t gamma_rule;               // 0 default, 1 tuned (Algorithm 3)
+    double p;                         // exponent of the tuned rule
     double eps, gamma_user, tol_user, A_user;
 };
 

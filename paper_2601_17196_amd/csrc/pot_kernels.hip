@@ -731,45 +731,52 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
 // setup (Algorithm 2, "Approximating POT"), validation, state initialisation
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
-    __shared__ double s_red[64];
-    __shared__ double s_v[4];
+    __shared__ double s_red[16 * 5];
+    __shared__ double s_v[5];
     Ctl& c = *S.ws.ctl;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const SetupIn in = {S.n, S.m, S.algo, S.s, S.eps, S.gamma_user, S.tol_user, S.A_user, S.cmax, S.cost_scale, S.w0};
-    // block reduction of three sums over the 1024 threads (16 waves)
-    auto reduce3 = [&](double (&v)[3]) {
+    const SetupIn in = {S.n, S.m, S.algo, S.gamma_rule, S.p, S.s, S.eps, S.gamma_user, S.tol_user, S.A_user,
+                        S.cmax, S.cost_scale, S.w0};
+    // block reduction of K sums over the 1024 threads (16 waves)
+    auto reduce = [&](auto& v) {
+        constexpr int K = sizeof(v) / sizeof(double);
         const int lane = tid & 63, wave = tid >> 6;
         __syncthreads();
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < K; ++k) {
             double x = wave_sum(v[k]);
-            if (lane == 0) s_red[wave * 3 + k] = x;
+            if (lane == 0) s_red[wave * K + k] = x;
         }
         __syncthreads();
         if (tid == 0) {
-            double a[3] = {0, 0, 0};
-            for (int w = 0; w < nt / 64; ++w)
-                for (int k = 0; k < 3; ++k) a[k] += s_red[w * 3 + k];
-            s_v[0] = a[0]; s_v[1] = a[1]; s_v[2] = a[2];
+            for (int k = 0; k < K; ++k) {
+                double a = 0.0;
+                for (int w = 0; w < nt / 64; ++w) a += s_red[w * K + k];
+                s_v[k] = a;
+            }
         }
         __syncthreads();
-        for (int k = 0; k < 3; ++k) v[k] = s_v[k];
+        for (int k = 0; k < K; ++k) v[k] = s_v[k];
     };
-    // sums and validity of the masses
-    double v[3] = {0.0, 0.0, 0.0};      // |r|_1, |c|_1, bad entries
+    // sums, entropies and validity of the masses
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};      // |r|_1, |c|_1, bad entries, H(r), H(c)
     for (int i = tid; i < S.n; i += nt) {
         double x = S.r[i];
         v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
         v[0] += x;
+        v[3] += ent(x);
     }
     for (int j = tid; j < S.m; j += nt) {
         double x = S.c[j];
         v[2] += (isfinite(x) && x >= 0.0) ? 0.0 : 1.0;
         v[1] += x;
+        v[4] += ent(x);
     }
-    reduce3(v);
+    reduce(v);
     const double sr = v[0], sc = v[1];
     double gamma, et, tol;
-    int valid = setup_params(in, sr, sc, v[2], gamma, et, tol);
+    int valid = setup_params(in, sr, sc, v[2], v[3], v[4], gamma, et, tol);
+    // every exponent log2(e) C_ij / gamma must stay below 2^29 (exponent split)
+    if (valid == 0 && !(kLog2e * S.cmax / gamma < 536870912.0)) valid = 7;
     // smoothed marginals r~, c~ (and their logs)
     double u[3] = {0.0, 0.0, 0.0};      // |r~|_1, |c~|_1, non-positive entries
     for (int i = tid; i < S.n; i += nt) {
@@ -786,7 +793,7 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
         u[2] += x > 0.0 ? 0.0 : 1.0;
         u[1] += x;
     }
-    reduce3(u);
+    reduce(u);
     if (valid == 0 && u[2] > 0.0) valid = 5;
     // Sinkhorn state a = 0, b = 0 (b lives in vz)
     if (S.algo == POT_SINKHORN) {

@@ -50,7 +50,7 @@ class Options(ct.Structure):
                 ("flags", ct.c_uint32), ("u0", ct.c_void_p), ("v0", ct.c_void_p), ("w0", ct.c_double),
                 ("force", ct.c_void_p), ("force_len", ct.c_int32), ("trace_i", ct.c_void_p),
                 ("trace_d", ct.c_void_p), ("trace_cap", ct.c_int32), ("tile_rows", ct.c_int32),
-                ("member_elems", ct.c_int32)]
+                ("member_elems", ct.c_int32), ("gamma_rule", ct.c_int32), ("p", ct.c_double)]
 
 
 class BatchOutputs(ct.Structure):
@@ -176,7 +176,7 @@ def make_problem(r, c, s, C=None, x=None, y=None, kind=None, ldc=None, cost_scal
 
 def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, block_rule=0,
                  step_rule=0, check_every=0, flags=0, u0=None, v0=None, w0=0.0, force=None,
-                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0, member_elems=0):
+                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0, member_elems=0, gamma_rule=0, p=1.0):
     o = Options()
     o.algo = int(algo)
     o.max_iter = int(max_iter)
@@ -196,6 +196,8 @@ def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, bl
     o.trace_cap = int(trace_cap)
     o.tile_rows = int(tile_rows)
     o.member_elems = int(member_elems)
+    o.gamma_rule = int(gamma_rule)
+    o.p = float(p)
     return o
 
 

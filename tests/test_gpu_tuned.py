@@ -1,0 +1,87 @@
+"""The tuned rule of Algorithm 3 (Theorem 2) on the HIP path, against the FP64
+oracle, through the C ABI: gamma = (2 eps / (49 H_min))^(1/p) and the
+stopping threshold eps' = H_min gamma^p, H_min = min(H(r), H(c)).
+
+gamma and eps' come from the device's own entropy sums and must equal the
+oracle's to rounding; the solve then follows the feasible Sinkhorn with the
+same bars as the default rule (1e-6 relative cost where both sides take the
+same number of iterations, else both stop at E <= eps' with the costs within
+eps), and the plan is exactly feasible.
+"""
+import numpy as np
+import pytest
+
+from oracle import potref as O
+from paper_2601_17196_amd import instances as I
+from tests.gpu_common import feasible, gpu_solve, oracle_cost_matrix, rel
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "u300x257": lambda: I.uniform_pair(300, 257, 2, 5, mass_r=1.0, mass_c=1.3, s_frac=0.7),
+    "u513x130dir05": lambda: I.uniform_pair(513, 130, 2, 7, mass_r=1.2, mass_c=0.8, s_frac=0.9, dirichlet=0.5),
+    "u70x1000": lambda: I.uniform_pair(70, 1000, 3, 6, mass_r=0.9, mass_c=1.1, s_frac=0.6),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("p", [1.0, 2.0, 3.0])
+def test_tuned_sinkhorn_matches_oracle(name, p):
+    inst = CASES[name]()
+    print(f"tuned sinkhorn {name} p={p}", flush=True)
+    C = oracle_cost_matrix(inst, "f32")
+    ref = O.solve(C, inst.r, inst.c, inst.s, inst.eps, algo="sinkhorn", cmax=1.0, gamma_rule=1, p=p, dense=True)
+    out = gpu_solve(inst, "f32", "sinkhorn", want_plan=True, gamma_rule=1, p=p)
+    res = out.result
+    assert out.status == 0
+    assert rel(res["gamma"], ref.gamma) <= 1e-13
+    assert rel(res["tol"], ref.tol) <= 1e-13
+    assert res["E"] <= res["tol"]
+    X = out.plan.cpu().numpy()
+    assert feasible(X, inst.r, inst.c, inst.s)
+    if res["iters"] == ref.iters:
+        assert rel(res["cost"], ref.rounded["cost"]) <= 1e-6
+    else:
+        assert abs(res["iters"] - ref.iters) <= 1
+        assert abs(res["cost"] - ref.rounded["cost"]) <= inst.eps
+
+
+def test_tuned_rule_rejected_where_undefined():
+    from paper_2601_17196_amd import pot
+    inst = CASES["u300x257"]()
+    # ASPOT has no tuned rule
+    out = gpu_solve(inst, "f32", "aspot", gamma_rule=1, p=2.0)
+    assert out.status == pot.ERR_INVALID_ARG
+    # p < 1
+    out = gpu_solve(inst, "f32", "sinkhorn", gamma_rule=1, p=0.5)
+    assert out.status == pot.ERR_INVALID_ARG
+    # a point mass has entropy 0: gamma is undefined
+    one = I.uniform_pair(1, 40, 2, 3, mass_r=1.0, mass_c=1.0, s_frac=0.5)
+    one.r = np.array([1.0])
+    out = gpu_solve(one, "f32", "sinkhorn", gamma_rule=1, p=2.0)
+    assert out.status == pot.ERR_INVALID_ARG
+    assert "H(r)" in pot.last_error()
+
+
+def test_tuned_rule_batched_equals_single():
+    """pot_solve_batched applies the same rule per instance (its own entropy
+    sums): gamma, tol and the cost match the single-instance solves."""
+    import torch
+
+    from paper_2601_17196_amd import pot
+    insts = [CASES[k]() for k in sorted(CASES)]
+    probs = []
+    for inst in insts:
+        d = pot.to_device_instance(inst, "cuda:0", kind="f32")
+        probs.append(dict(r=d["r"], c=d["c"], s=d["s"], C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0))
+    st, res, _ = pot.solve_batched(probs, insts[0].eps, algo=pot.SINKHORN, gamma_rule=1, p=2.0)
+    torch.cuda.synchronize()
+    assert st == 0
+    for inst, r in zip(insts, res):
+        one = gpu_solve(inst, "f32", "sinkhorn", gamma_rule=1, p=2.0).result
+        assert r["status"] == 0
+        assert rel(r["gamma"], one["gamma"]) <= 1e-13 and rel(r["tol"], one["tol"]) <= 1e-13
+        if r["iters"] == one["iters"]:
+            assert rel(r["cost"], one["cost"]) <= 1e-6
+        else:
+            assert abs(r["cost"] - one["cost"]) <= inst.eps

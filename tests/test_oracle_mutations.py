@@ -45,6 +45,11 @@ MUTATIONS = {
     "form_primal_sign": ("X[(size_t)i * m + j] = exp(f[i] + g[j] - C[(long)i * ldc + j] * ig);",
                          "X[(size_t)i * m + j] = exp(f[i] - g[j] - C[(long)i * ldc + j] * ig);"),
     "rho_series_sign": ("double add = ((k & 1) ? -term : term) / k;", "double add = term / k;"),
+    "tuned_max_entropy": ("double h = hr < hc ? hr : hc;", "double h = hr > hc ? hr : hc;"),
+    "tuned_missing_root": ("double gamma = pow(2.0 * eps / (49.0 * h), 1.0 / p);",
+                           "double gamma = 2.0 * eps / (49.0 * h);"),
+    "tuned_log2_entropy": ("if (r[i] > 0.0) hr -= r[i] * log(r[i]);", "if (r[i] > 0.0) hr -= r[i] * log2(r[i]);"),
+    "tuned_threshold_p": ("out3[1] = h * pow(gamma, p);", "out3[1] = h * gamma;"),
 }
 
 

@@ -550,3 +550,65 @@ def test_cost_compensated_sum(oracle):
     X[0, 0] = 1e16
     X[0, 1] = -1e16
     assert oracle.cost(C, X) == pytest.approx(1.0, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# tuned rule of Algorithm 3 (Theorem 2): gamma = (2 eps / (49 H_min))^(1/p),
+# eps' = H_min gamma^p, H_min = min(H(r), H(c))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [1.0, 2.0, 3.0, 4.5])
+def test_tuned_rule_uniform_marginals(oracle, p):
+    """Uniform marginals have H = ln n (a closed form, not the code's sum):
+    H_min = ln 8 for n = 8 against m = 16; gamma^p 49 H_min / 2 = eps, and
+    eps' = 2 eps / 49 whatever p."""
+    eps = 1e-2
+    g, tol, h = oracle.tuned(np.full(8, 1 / 8), np.full(16, 1 / 16), eps, p)
+    assert abs(h - math.log(8)) <= 1e-14
+    assert abs(g ** p * 49 * math.log(8) / 2 - eps) <= 1e-13 * eps
+    assert abs(tol - 2 * eps / 49) <= 1e-13 * eps
+
+
+def test_tuned_rule_entropy_conventions(oracle):
+    """0 ln 0 = 0: r = (1/2, 1/2, 0) has H = ln 2; the masses enter as given
+    (not normalised): n equal masses a give H = -n a ln a; the smaller
+    entropy of the two sides is taken."""
+    _, _, h = oracle.tuned(np.array([0.5, 0.5, 0.0]), np.full(5, 0.2), 1e-2, 1)
+    assert abs(h - math.log(2)) <= 1e-15
+    a = 0.3
+    _, _, h = oracle.tuned(np.full(4, a), np.full(50, 0.02), 1e-2, 2)
+    assert abs(h - (-4 * a * math.log(a))) <= 1e-14
+    _, _, h2 = oracle.tuned(np.full(50, 0.02), np.full(4, a), 1e-2, 2)
+    assert h2 == h
+
+
+def test_tuned_rule_rejects(oracle):
+    with pytest.raises(ValueError):
+        oracle.tuned(np.array([1.0]), np.full(3, 1 / 3), 1e-2, 1)      # H(r) = 0
+    with pytest.raises(ValueError):
+        oracle.tuned(np.full(3, 1 / 3), np.full(3, 1 / 3), 1e-2, 0.5)  # p < 1
+    with pytest.raises(ValueError):
+        oracle.solve(np.ones((3, 3)), np.full(3, 1 / 3), np.full(3, 1 / 3), 0.5, 1e-2, algo="aspot",
+                     gamma_rule=1, p=2)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_tuned_sinkhorn_vs_exact_lp(oracle, seed):
+    """The tuned Sinkhorn (smoothing and extension as the default feasible
+    Sinkhorn, only gamma and the threshold change) returns a feasible plan,
+    stops at E <= eps'; for p = 1, 2 it is within eps of the exact LP.
+    Larger p needs far fewer iterations (the trend the paper reports)."""
+    n, m = (6, 7) if seed == 1 else (8, 8)
+    inst = I.uniform_pair(n, m, 2, seed, mass_r=1.0, mass_c=1.2, s_frac=0.8)
+    lp = pot_lp(inst.C64, inst.r, inst.c, inst.s)[0]
+    iters = []
+    for p in (1, 2, 3):
+        sol = oracle.solve(inst.C64, inst.r, inst.c, inst.s, inst.eps, algo="sinkhorn", gamma_rule=1, p=p,
+                           cmax=1.0, dense=True)
+        g, tol, _ = oracle.tuned(inst.r, inst.c, inst.eps, p)
+        assert sol.gamma == g and sol.tol == tol and sol.status == 0 and sol.E <= tol
+        assert in_polytope(sol.rounded["X"], inst.r, inst.c, inst.s)
+        assert sol.rounded["cost"] >= lp - 1e-12
+        if p <= 2:
+            assert sol.rounded["cost"] - lp <= inst.eps
+        iters.append(sol.iters)
+    assert iters[0] > iters[1] > iters[2]
