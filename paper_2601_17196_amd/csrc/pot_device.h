@@ -106,30 +106,24 @@ __device__ __forceinline__ void lse_merge(double& m1, double& s1, double m2, dou
     else s1 = s1 + s2 * exp(m2 - m1);
 }
 
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ __forceinline__ void lse_step(double& m, double& s) {
-    const double m2 = dpp_d<CTRL, ROW_MASK>(m, -INFINITY), s2 = dpp_d<CTRL, ROW_MASK>(s, 0.0);
-    lse_merge(m, s, m2, s2);
-}
-
 // log-sum-exp pair over the NW waves of the block; the result is returned
-// to every thread
+// to every thread.  The block maximum M first (DPP wave maxima, then the
+// waves in LDS), then every thread rescales its own pair once,
+// s exp(m - M), and the rescaled sums are added in the fixed order of
+// block_sum: one exponential per thread instead of a chain of merges.
 template <int NW = 4>
 __device__ inline void block_lse(double& m, double& s, double* lds /* >= 2*NW */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    lse_step<kQuadX1>(m, s);
-    lse_step<kQuadX2>(m, s);
-    lse_step<kHalfMirror>(m, s);
-    lse_step<kMirror>(m, s);
-    lse_step<kBcast15, 0xA>(m, s);
-    lse_step<kBcast31, 0xC>(m, s);
-    m = readlane_d(m, 63);
-    s = readlane_d(s, 63);
-    if (lane == 0) { lds[2 * wave] = m; lds[2 * wave + 1] = s; }
+    double M = wave_max(m);
+    if (lane == 0) lds[wave] = M;
     __syncthreads();
-    m = lds[0];
-    s = lds[1];
-    for (int w = 1; w < NW; ++w) lse_merge(m, s, lds[2 * w], lds[2 * w + 1]);
+    M = lds[0];
+    for (int w = 1; w < NW; ++w) M = fmax(M, lds[w]);
+    const double t = wave_sum(m == -INFINITY ? 0.0 : s * exp(m - M));
+    if (lane == 0) lds[NW + wave] = t;
+    __syncthreads();
+    s = wave_tree<NW>(lds + NW, 1);
+    m = M;
     __syncthreads();
 }
 

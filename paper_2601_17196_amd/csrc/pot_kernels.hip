@@ -37,39 +37,75 @@ __device__ void gather_strips(const double* part, int nstrips, double (&tot)[kSc
     block_sum<kScal>(tot, lds);
 }
 
-__device__ void decide(const PassArgs& A, Ctl& cs, double* lds) {
+__device__ void decide(const PassArgs& A, Ctl& cs, double* lds /* >= 17 */) {
     double Rs[kScal], Cs[kScal];
     const bool rows = A.phase != PH_SK_COL;
     const bool cols = A.phase != PH_SK_ROW;
     const bool sk = A.phase == PH_SK_ROW || A.phase == PH_SK_COL;
     {
-        // every block's sums in one batch of loads; Sinkhorn passes also merge
-        // the blocks' (max, sum of exp) pairs (one side only) in a fixed tree
-        const int nr = rows ? A.nrb : 0, nb = nr + (cols ? A.ncb : 0);
-        double v[2 * kScal];
+        // Every block's sums, added in a fixed order.  The 16 groups of 16
+        // lanes (one DPP row each) take one slot each: group k, lane g sums
+        // slot k % 8 of side k / 8 (row blocks, column blocks) over blocks g,
+        // g + 16, ..., loading 8 blocks per batch, and the row is then reduced
+        // in 4 DPP steps.  A Sinkhorn pass has one side (groups 0..7); its
+        // group 1 merges the blocks' (max, sum of exp) pairs of slots 1 and 2:
+        // running maximum per lane, then the row maximum, then one rescaling
+        // exponential per lane before the row sum.
+        const int tid = threadIdx.x, k = tid >> 4, g = tid & 15;
+        const int side = sk ? (rows ? 0 : 1) : (k >> 3);
+        const int slot = k & 7;
+        const bool pair = sk && slot == 1;
+        const int nside = (sk && k >= 8) ? 0 : (side == 0 ? (rows ? A.nrb : 0) : (cols ? A.ncb : 0));
+        const double* base = side == 0 ? A.ws.rowscal : A.ws.colscal;
+        double v = 0.0, m = -INFINITY;
+        for (int b0 = g; b0 < nside; b0 += 16 * 8) {
+            double x[8], y[8];
 #pragma unroll
-        for (int k = 0; k < 2 * kScal; ++k) v[k] = 0.0;
-        double mx = -INFINITY, se = 0.0;
-        for (int b = threadIdx.x; b < nb; b += kThreads) {
-            const bool isr = b < nr;
-            const double* p = isr ? A.ws.rowscal + (int64_t)b * kScal : A.ws.colscal + (int64_t)(b - nr) * kScal;
-            double x[kScal];
-#pragma unroll
-            for (int k = 0; k < kScal; ++k) x[k] = ld_agent(&p[k]);
-#pragma unroll
-            for (int k = 0; k < kScal; ++k) {
-                v[k] += isr ? x[k] : 0.0;
-                v[kScal + k] += isr ? 0.0 : x[k];
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + 16 * u;
+                x[u] = b < nside ? ld_agent(&base[(int64_t)b * kScal + slot]) : (pair ? -INFINITY : 0.0);
+                y[u] = (pair && b < nside) ? ld_agent(&base[(int64_t)b * kScal + 2]) : 0.0;
             }
-            if (sk) lse_merge(mx, se, x[1], x[2]);
-        }
-        block_sum<2 * kScal>(v, lds);
-        if (sk) block_lse(mx, se, lds);
+            if (pair) {
+                double bm = m;
 #pragma unroll
-        for (int k = 0; k < kScal; ++k) { Rs[k] = v[k]; Cs[k] = v[kScal + k]; }
+                for (int u = 0; u < 8; ++u) bm = fmax(bm, x[u]);
+                if (bm != -INFINITY) {
+                    double acc = m == -INFINITY ? 0.0 : v * exp(m - bm);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc += x[u] == -INFINITY ? 0.0 : y[u] * exp(x[u] - bm);
+                    m = bm;
+                    v = acc;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += x[u];
+            }
+        }
+        double M = -INFINITY;
         if (sk) {
-            if (rows) { Rs[1] = mx; Rs[2] = se; }
-            else { Cs[1] = mx; Cs[2] = se; }
+            M = m;
+            M = fmax(M, dpp_d<kQuadX1>(M, M));
+            M = fmax(M, dpp_d<kQuadX2>(M, M));
+            M = fmax(M, dpp_d<kHalfMirror>(M, M));
+            M = fmax(M, dpp_d<kMirror>(M, M));
+            if (pair) v = (m == -INFINITY) ? 0.0 : v * exp(m - M);
+        }
+        v += dpp_d<kQuadX1>(v, 0.0);
+        v += dpp_d<kQuadX2>(v, 0.0);
+        v += dpp_d<kHalfMirror>(v, 0.0);
+        v += dpp_d<kMirror>(v, 0.0);
+        if (g == 0) lds[k] = v;
+        if (pair && g == 0) lds[16] = M;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScal; ++j) {
+            Rs[j] = sk ? (rows ? lds[j] : 0.0) : lds[j];
+            Cs[j] = sk ? (cols ? lds[j] : 0.0) : lds[kScal + j];
+        }
+        if (sk) {
+            if (rows) { Rs[1] = lds[16]; Rs[2] = lds[1]; }
+            else { Cs[1] = lds[16]; Cs[2] = lds[1]; }
         }
     }
     if (threadIdx.x == 0) {
