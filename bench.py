@@ -172,28 +172,67 @@ def bench_warm(pot, I, dev, eps, reps, plain_sample):
     return out
 
 
-def cpu_baseline(inst, iters_full, eps, budget_iters):
+def cpu_baseline(inst, iters_full, eps, budget_iters, one_core_iters=2):
     """The FP64 oracle (as it stands) timed on the host cores on a bounded
     sample: `budget_iters` ASPOT iterations of the same instance, scaled to
-    solves/s with the full solve's iteration count."""
+    solves/s with the full solve's iteration count; then `one_core_iters`
+    iterations on one thread."""
     import numpy as np
 
     from oracle import potref
     C = inst.C32.astype(np.float64)
     gam, tol, M, rt, ct_ = potref.setup(inst.r, inst.c, inst.s, eps, cmax=1.0)
+    cores = potref.threads()
     t0 = time.perf_counter()
     potref.aspot(C, gam, tol, rt, ct_, inst.s, M, max_iter=budget_iters)
     dt = time.perf_counter() - t0
     per_iter = dt / budget_iters
+    potref.set_threads(1)
+    t0 = time.perf_counter()
+    potref.aspot(C, gam, tol, rt, ct_, inst.s, M, max_iter=one_core_iters)
+    dt1 = time.perf_counter() - t0
+    potref.set_threads(cores)
+    per_iter1 = dt1 / one_core_iters
     return {
         "value": 1.0 / (per_iter * iters_full),
         "unit": "solves/s",
-        "cores": potref.threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": (f"{budget_iters} ASPOT iterations of the same n=m={inst.n} instance "
                    f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled by the full solve's "
-                   f"{iters_full} iterations"),
+                   f"{iters_full} iterations; on 1 core {one_core_iters} iterations "
+                   f"({per_iter1 * 1e3:.0f} ms/iteration)"),
+        "value_1core": 1.0 / (per_iter1 * iters_full),
     }
+
+
+def bench_shard(pot, I, dev, eps):
+    """The statistics pass on one GPU's share of the 20000^2 instance split by
+    rows over 8 GPUs: rows 0..2499 of its cost against all 20000 columns
+    (FP32, the same normalisation), solved as an instance of its own (source
+    masses rescaled to total 1, s = 0.7) to get representative duals, then
+    the pass timed at them."""
+    import numpy as np
+    import torch
+    inst = I.c3(0, dense=False)
+    ns, m = inst.n // 8, inst.m
+    x = torch.from_numpy(inst.x[:ns].astype(np.float64)).to(dev)
+    y = torch.from_numpy(inst.y.astype(np.float64)).to(dev)
+    D = torch.zeros((ns, m), dtype=torch.float64, device=dev)
+    for k in range(x.shape[1]):
+        diff = x[:, k:k + 1] - y[None, :, k]
+        D += diff * diff
+    C = (D * inst.cost_scale).to(torch.float32)
+    del D
+    r = torch.full((ns,), 1.0 / ns, dtype=torch.float64, device=dev)
+    c = torch.from_numpy(inst.c).to(dev)
+    o = pot.solve(r, c, 0.7, eps, C=C, cmax=1.0, want_factors=False)
+    ms = pot.time_pass(r, c, 0.7, eps, reps=20, C=C, cmax=1.0, u0=o.u, v0=o.v, w0=o.w)[0]
+    gbs = ns * m * 4 / (ms * 1e-3) / 1e9
+    nx, ny = (m + 255) // 256, (ns + 127) // 128
+    return {"n": ns, "m": m, "iters": o.result["iters"], "tile_kernel_us": ms * 1e3, "GB_per_s": gbs,
+            "frac_hbm": gbs / HBM_PEAK_GBS, "column_partials_bytes": ny * m * 8,
+            "allreduce_bytes_per_pass": (m + 3) * 8}
 
 
 def main():
@@ -304,6 +343,10 @@ def main():
             log(f"{name}: {extra[name]}")
             del d2
             torch.cuda.empty_cache()
+        log("shard: rows 0..2499 of the 20000^2 instance (one GPU of 8)")
+        extra["c3_shard_2500x20000"] = bench_shard(pot, I, dev, eps)
+        log(f"shard: {extra['c3_shard_2500x20000']}")
+        torch.cuda.empty_cache()
         # the tuned rule of Algorithm 3 (Theorem 2) on the same instance; its
         # cost is compared with the ASPOT cost (within eps of the optimum)
         if args.kind == "f32":

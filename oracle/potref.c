@@ -31,6 +31,14 @@ int potref_threads(void) {
 #endif
 }
 
+void potref_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* log(e^a + e^b) */
 static double logaddexp(double a, double b) {
     if (a == -INFINITY) return b;

@@ -141,6 +141,9 @@ double potref_cost(int n, int m, const double* C, long ldc, const double* X);
 /* Number of OpenMP threads the oracle uses. */
 int potref_threads(void);
 
+/* Sets the OpenMP thread count of later calls (t > 0). */
+void potref_set_threads(int t);
+
 #ifdef __cplusplus
 }
 #endif

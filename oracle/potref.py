@@ -30,6 +30,7 @@ __all__ = [
     "cost",
     "solve",
     "threads",
+    "set_threads",
     "AspotTrace",
     "OracleSolution",
 ]
@@ -110,6 +111,8 @@ def load():
     lib.potref_cost.restype = ct.c_double
     lib.potref_threads.argtypes = []
     lib.potref_threads.restype = ct.c_int
+    lib.potref_set_threads.argtypes = [ct.c_int]
+    lib.potref_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -128,6 +131,11 @@ def _f64(a):
 
 def threads() -> int:
     return int(load().potref_threads())
+
+
+def set_threads(t: int) -> None:
+    """OpenMP threads of later oracle calls."""
+    load().potref_set_threads(int(t))
 
 
 def setup(r, c, s, eps, cmax=1.0, gamma=0.0, tol=0.0):
