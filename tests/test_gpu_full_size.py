@@ -1,5 +1,5 @@
 """The full-size single instance (n = m = 20000, 2-D shifted mixtures,
-s = 0.7, eps = 1e-2) through pot_solve, FP32 and BF16 costs.
+s = 0.7, eps = 1e-2 and 5e-3) through pot_solve, FP32 and BF16 costs.
 
 The oracle cannot solve this size, so the checks are those that hold at any
 size or that the oracle computes one output at a time:
@@ -34,12 +34,13 @@ def _device_cost(inst, dtype):
     return C if dtype == "f32" else C.view(torch.int16)
 
 
-def test_full_size_instance():
+@pytest.mark.parametrize("eps", [1e-2, 5e-3])
+def test_full_size_instance(eps):
     import torch
 
     from paper_2601_17196_amd import pot
-    inst = I.c3(0, dense=False)
-    print(f"full size: n = m = {inst.n}", flush=True)
+    inst = I.c3(0, eps=eps, dense=False)
+    print(f"full size: n = m = {inst.n}, eps = {eps}", flush=True)
     r = torch.from_numpy(inst.r).cuda()
     c = torch.from_numpy(inst.c).cuda()
     C32 = _device_cost(inst, "f32")
