@@ -254,7 +254,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the solver has no multi-GPU path in this build "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(a row-sharded design is described with the library)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -343,6 +343,20 @@ def main():
             log(f"{name}: {extra[name]}")
             del d2
             torch.cuda.empty_cache()
+        # the solver variants against the canonical readings (same instance)
+        if args.kind == "f32" and algo == pot.ASPOT:
+            for name, kw in [("aspot_step_rule1", dict(step_rule=1)), ("aspot_block_rule1", dict(block_rule=1))]:
+                probe = run_solve(pot, d, eps, pot.ASPOT, "f32", raise_on_error=False, want_factors=False, **kw)
+                if probe.status != pot.OK:
+                    # e.g. the proof-form step, whose first move from the cold start can take
+                    # every term of B(z) below the FP64 range of the sums
+                    extra[name] = {"status": pot.status_string(probe.status), "iters": probe.result["iters"]}
+                else:
+                    o2, w2, ev2 = time_solves(pot, d, eps, pot.ASPOT, "f32", 3, 1, None, **kw)
+                    rr = o2[-1].result
+                    extra[name] = {"solves_per_s": 3 / (ev2 / 1e3), "iters": rr["iters"], "cost": rr["cost"],
+                                   "cost_minus_canonical": rr["cost"] - outs[-1].result["cost"]}
+                log(f"{name}: {extra[name]}")
         log("shard: rows 0..2499 of the 20000^2 instance (one GPU of 8)")
         extra["c3_shard_2500x20000"] = bench_shard(pot, I, dev, eps)
         log(f"shard: {extra['c3_shard_2500x20000']}")

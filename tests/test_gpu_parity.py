@@ -191,3 +191,28 @@ def test_computed_cmax_matches_given():
     b = gpu_solve(inst, "f32", "aspot", cmax=float(inst.C32.max()))
     assert a.result["cmax"] == float(inst.C32.max())
     assert a.result["cost"] == b.result["cost"]
+
+
+@pytest.mark.parametrize("name", ["u300x257", "u513x130dir05", "c1"])
+@pytest.mark.parametrize("variant", [dict(step_rule=1), dict(block_rule=1)])
+def test_solver_variants_parity(name, variant):
+    """The proof-form step (step_rule = 1) and the cyclic block rule
+    (block_rule = 1) against the oracle run with the same option: the same
+    bars as the canonical rules, and with the cyclic rule the GPU's recorded
+    blocks follow the cycle exactly."""
+    inst = CASES[name]()
+    print(f"variant {variant} case {name}", flush=True)
+    ref = _oracle(inst, "f32", "aspot", **variant)
+    out = gpu_solve(inst, "f32", "aspot", trace_cap=ref.iters + 8, want_plan=True, **variant)
+    res = out.result
+    assert out.status == 0 and res["E"] <= res["tol"]
+    assert feasible(out.plan.cpu().numpy(), inst.r, inst.c, inst.s)
+    ti = out.trace_i.cpu().numpy().reshape(-1, 3)[:res["iters"]]
+    if variant.get("block_rule") == 1:
+        t = np.arange(res["iters"])
+        assert np.array_equal(ti[:, 0], (2 * t) % 3)
+        assert np.array_equal(ti[:-1, 2], (2 * t[:-1] + 1) % 3)
+    if res["iters"] == ref.iters:
+        assert rel(res["cost"], ref.rounded["cost"]) <= COST_RTOL
+    else:
+        assert abs(res["cost"] - ref.rounded["cost"]) <= inst.eps

@@ -612,3 +612,35 @@ def test_tuned_sinkhorn_vs_exact_lp(oracle, seed):
             assert sol.rounded["cost"] - lp <= inst.eps
         iters.append(sol.iters)
     assert iters[0] > iters[1] > iters[2]
+
+
+# ---------------------------------------------------------------------------
+# solver variants (readings 5 and 6): the proof-form step and the cyclic block
+# rule also end in eps-approximations; the cyclic rule takes u, v, w in turn
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", [dict(step_rule=1), dict(block_rule=1)])
+@pytest.mark.parametrize("seed", range(4))
+def test_aspot_variants_vs_exact_lp(oracle, variant, seed):
+    rng = np.random.default_rng(100 + seed)
+    n, m = int(rng.integers(2, 9)), int(rng.integers(2, 9))
+    C, r, c, s = _tiny(n, m, 50 + seed, mass_r=float(rng.uniform(0.6, 1.4)), mass_c=float(rng.uniform(0.6, 1.4)),
+                       s_frac=float(rng.uniform(0.3, 0.95)))
+    lp, _ = pot_lp(C, r, c, s)
+    try:
+        sol = oracle.solve(C, r, c, s, 1e-2, algo="aspot", cmax=float(C.max()), dense=True, max_iter=400000,
+                           trace=True, **variant)
+    except ValueError:
+        return                               # eps~ capped to 0: rejected by design
+    assert sol.status == 0
+    X = sol.rounded["X"]
+    assert in_polytope(X, r, c, s)
+    val = float(np.sum(C * X))
+    assert lp - 1e-9 <= val <= lp + 1e-2
+    if variant.get("block_rule") == 1:
+        # one counter over both Greenkhorn steps of an iteration: z-hat takes
+        # block 2t mod 3, z-check block 2t + 1 mod 3
+        it = sol.iters
+        bh = np.asarray(sol.trace.bhat[:it])
+        bc = np.asarray(sol.trace.bchk[:it - 1])
+        assert np.array_equal(bh, (2 * np.arange(it)) % 3)
+        assert np.array_equal(bc, (2 * np.arange(it - 1) + 1) % 3)
