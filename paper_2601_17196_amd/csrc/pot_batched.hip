@@ -378,8 +378,8 @@ __device__ bool member_pass(Member& M, BShared& S) {
     } else {
         // rows and columns side by side (one element per thread at the sizes of a batch)
         for (int k = tid; k < nr + m; k += kBThreads) {
-            if (k < nr) aspot_step<PH>(A, true, r0 + k, S.R[k], load_step<PH>(A, true, r0 + k), Rs);
-            else aspot_step<PH>(A, false, k - nr, S.Q[k - nr], load_step<PH>(A, false, k - nr), Cs);
+            if (k < nr) aspot_step<PH>(A, true, r0 + k, S.R[k], 0, S.R[k], load_step<PH>(A, true, r0 + k), Rs);
+            else aspot_step<PH>(A, false, k - nr, S.Q[k - nr], 0, 0.0, load_step<PH>(A, false, k - nr), Cs);
         }
         block_sum<kScal, kBWaves>(Rs, S.red);
         block_sum<kScal, kBWaves>(Cs, S.red);

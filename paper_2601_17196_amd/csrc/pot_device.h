@@ -182,6 +182,13 @@ __device__ inline double rho_ab(double a, double b) {
     return a * h;
 }
 
+// rho(a, b) given also lb = log b, for a b that left the normal FP64 range
+// (a total whose every term underflowed): b - a - a (log b - log a)
+__device__ inline double rho_abl(double a, double b, double lb) {
+    if (b >= 2.2250738585072014e-308 && b <= 1.7976931348623157e308) return rho_ab(a, b);
+    return (b - a) - a * (lb - log(a));
+}
+
 // ---------------------------------------------------------------------------
 // cost access
 // ---------------------------------------------------------------------------
@@ -342,7 +349,8 @@ __device__ __forceinline__ double w_point(const PassArgs& A, const Ctl& c) {
 // reads is loaded (`load_step`) before the control block, together with the
 // tile partials, so that the pass makes a single round trip to memory.
 // acc slots: 0 T-part, 1 sum e^u, 2 <u, r~>, 3 <du, r~>, 4 rho score,
-//            5 E part, 6 spare, 7 non-finite count
+//            5 E part, 6 binary exponent of slot 0 (T = slot0 * 2^slot6),
+//            7 non-finite count
 // ---------------------------------------------------------------------------
 struct StepPre {
     double x0, x1, x2, x3;
@@ -366,15 +374,18 @@ __device__ __forceinline__ StepPre load_step(const PassArgs& A, bool row, int i)
     return p;
 }
 
-// ASPOT step of row i (row) or column i: R is the row (column) sum of B at
-// the point of the pass, x0 the dual there, x1 the smoothed mass, x2 its log.
+// ASPOT step of row i (row) or column i.  The row (column) sum of B at the
+// point of the pass is R = Rm 2^Re (its value may leave the FP64 range; its
+// log stays exact), Tc the row's share of slot 0 (R scaled by the caller's
+// block exponent); x0 the dual there, x1 the smoothed mass, x2 its log.
 template <int PH>
-__device__ __forceinline__ void aspot_step(const PassArgs& A, bool row, int i, double R, const StepPre& p,
-                                           double* acc) {
+__device__ __forceinline__ void aspot_step(const PassArgs& A, bool row, int i, double Rm, int Re, double Tc,
+                                           const StepPre& p, double* acc) {
     const Ws& w = A.ws;
     const double x = p.x0, t = p.x1;
+    const double R = ldexp(Rm, Re);
     acc[7] += isfinite(R) ? 0.0 : 1.0;
-    if (row) acc[0] += R;
+    if (row) acc[0] += Tc;
     switch (PH) {
     case PH_INIT:
         acc[1] += exp(x); acc[2] += t * x;
@@ -385,11 +396,21 @@ __device__ __forceinline__ void aspot_step(const PassArgs& A, bool row, int i, d
         break;
     case PH_GRAVE:
     case PH_Z: {
-        const double ex = exp(x), b = R + ex, lb = log(b);
+        const double ex = exp(x), b = R + ex;
+        double lb = log(b), rh = rho_ab(t, b);
+        // R + e^u below the normal range (the row sum underflowed, and e^u
+        // with it): log(R + e^u) in the log domain.  (A wave-uniform test, so
+        // that the rare path is not evaluated on every row.)
+        if (__any(!(b >= 2.2250738585072014e-308))) {
+            if (!(b >= 2.2250738585072014e-308)) {
+                lb = logaddexp(log(Rm) + Re * kLn2, x);
+                rh = rho_abl(t, b, lb);
+            }
+        }
         const double d = p.x2 - lb;                 // Greenkhorn step: u + log r~ - log(B 1 + e^u)
         (row ? w.du : w.dv)[i] = d;
         acc[1] += ex; acc[2] += t * x; acc[3] += t * d;
-        acc[4] += rho_ab(t, b);
+        acc[4] += rh;
         acc[5] += fabs(b - t);
         break;
     }
@@ -413,12 +434,14 @@ __device__ inline int argmax3(double a, double b, double d) {
 //   u-step: |r~|_1 + sum e^v - <u', r~> - <v, c~> - w s
 //   v-step: |c~|_1 + sum e^u - <u, r~> - <v', c~> - w s
 //   w-step: s + sum e^u + sum e^v - <u, r~> - <v, c~> - w' s
-__device__ inline double phi_after(const Ctl& c, int block, const double* R, const double* Cc, double w) {
+// (lT = log T: the w-step stays exact where T itself left the FP64 range)
+__device__ inline double phi_after(const Ctl& c, int block, const double* R, const double* Cc, double w,
+                                   double lT) {
     switch (block) {
     case 0: return c.sum_rt + Cc[1] - (R[2] + R[3]) - Cc[2] - w * c.s;
     case 1: return c.sum_ct + R[1] - R[2] - (Cc[2] + Cc[3]) - w * c.s;
     default: {
-        double w1 = w + c.log_s - log(R[0]);
+        double w1 = w + c.log_s - lT;
         return c.s + R[1] + Cc[1] - R[2] - Cc[2] - w1 * c.s;
     }
     }
@@ -430,9 +453,16 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
     const int t = c.t, par = t & 1;
     // a non-finite sum, or (ASPOT) a total that underflowed even the FP64
     // range after the tiles' shifts: the statistics cannot be represented
+    // (ASPOT's total arrives as Rs[0] * 2^Rs[6]: its value T may leave the
+    // FP64 range while log T stays exact)
     const bool aspot_phase = A.phase == PH_INIT || A.phase == PH_BAR || A.phase == PH_GRAVE || A.phase == PH_Z;
     const bool bad = (rows && Rs[7] > 0.0) || (cols && Cs[7] > 0.0) ||
                      (aspot_phase && !(Rs[0] > 0.0 && isfinite(Rs[0])));
+    const double Tv = aspot_phase ? ldexp(Rs[0], (int)Rs[6]) : 0.0;
+    const bool T_normal = Tv >= 2.2250738585072014e-308 && Tv <= 1.7976931348623157e308;
+    auto logT = [&]() -> double { return T_normal ? log(Tv) : log(Rs[0]) + Rs[6] * kLn2; };
+    // rho(s, T): the w block's score
+    auto rho_w = [&]() -> double { return T_normal ? rho_ab(c.s, Tv) : (Tv - c.s) - c.s * (logT() - c.log_s); };
     if (bad) {
         c.nonfinite = 1;
         c.status = POT_ERR_NUMERIC;
@@ -442,8 +472,8 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
     }
     switch (A.phase) {
     case PH_INIT: {
-        c.T = Rs[0];
-        c.phichk = Rs[0] + Rs[1] + Cs[1] - Rs[2] - Cs[2] - A.w0 * c.s;
+        c.T = Tv;
+        c.phichk = Tv + Rs[1] + Cs[1] - Rs[2] - Cs[2] - A.w0 * c.s;
         c.wchk[0] = A.w0;
         c.wtil[0] = A.w0;
         c.theta = 1.0;
@@ -451,7 +481,7 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
         break;
     }
     case PH_BAR: {
-        double gw = Rs[0] - c.s;                         // d phi / d w at zbar
+        double gw = Tv - c.s;                            // d phi / d w at zbar
         double wb = (1.0 - c.theta) * pick2(c.wchk, par) + c.theta * pick2(c.wtil, par);
         double eta = (A.step_rule == 0 ? c.gamma : 1.0) / (3.0 * c.M * c.theta);
         double wt1 = (A.step_rule == 0 ? wb : pick2(c.wtil, par)) - eta * gw;
@@ -461,12 +491,11 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
         break;
     }
     case PH_GRAVE: {
-        double T = Rs[0];
-        double rho_w = rho_ab(c.s, T);
-        int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w) : (c.cyc++ % 3);
+        int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w()) : (c.cyc++ % 3);
         if (A.force && t < A.force_len) b = A.force[3 * t + 0];
-        double ph = phi_after(c, b, Rs, Cs, c.wgrave);
-        double wh = c.wgrave + (b == 2 ? c.log_s - log(T) : 0.0);
+        const double lT = b == 2 ? logT() : 0.0;
+        double ph = phi_after(c, b, Rs, Cs, c.wgrave, lT);
+        double wh = c.wgrave + (b == 2 ? c.log_s - lT : 0.0);
         int pick = ph < c.phichk ? 1 : 0;                // argmin, ties keep z-check
         if (A.force && t < A.force_len) pick = A.force[3 * t + 1];
         c.bhat = b;
@@ -485,7 +514,7 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
         break;
     }
     case PH_Z: {
-        double T = Rs[0];
+        double T = Tv;
         double E = fabs(T - c.s) + Rs[5] + Cs[5];        // E(z^t), Section 3.1
         c.E = E;
         c.T = T;
@@ -499,12 +528,12 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
             if (A.trace_i && t < A.trace_cap) A.trace_i[3 * t + 2] = -1;
             break;
         }
-        double rho_w = rho_ab(c.s, T);
-        int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w) : (c.cyc++ % 3);
+        int b = A.block_rule == 0 ? argmax3(Rs[4], Cs[4], rho_w()) : (c.cyc++ % 3);
         if (A.force && t < A.force_len) b = A.force[3 * t + 2];
         c.bchk = b;
-        c.phichk = phi_after(c, b, Rs, Cs, c.wz);
-        put2(c.wchk, par ^ 1, c.wz + (b == 2 ? c.log_s - log(T) : 0.0));
+        const double lT = b == 2 ? logT() : 0.0;
+        c.phichk = phi_after(c, b, Rs, Cs, c.wz, lT);
+        put2(c.wchk, par ^ 1, c.wz + (b == 2 ? c.log_s - lT : 0.0));
         if (A.trace_i && t < A.trace_cap) A.trace_i[3 * t + 2] = b;
         c.theta = c.theta * (sqrt(c.theta * c.theta + 4.0) - c.theta) / 2.0;
         c.t = t + 1;
@@ -635,6 +664,7 @@ __device__ inline void setup_fill(Ctl& c, const SetupIn& S, double gamma, double
     c.done = valid ? 1 : 0;
     c.status = valid ? POT_ERR_INVALID_ARG : POT_OK;
     c.bhat = c.pick = c.bchk = 0;
+    c.wide = 0;
     c.iters = 0;
     c.nonfinite = 0;
     c.out_par = 0;

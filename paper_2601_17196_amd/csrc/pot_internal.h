@@ -51,7 +51,8 @@ struct Ctl {
     int32_t out_par;       // Sinkhorn: parity slot of the output a
     int32_t cyc;           // cyclic block counter
     int32_t valid;         // setup status (0 ok)
-    int32_t pad_;
+    int32_t wide;          // a tile of the pass just made had its shift beyond the normal
+                           // FP64 window (set by the tile pass, cleared by the decider)
 };
 
 // Pointers into one solve's workspace.

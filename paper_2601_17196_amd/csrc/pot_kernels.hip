@@ -4,11 +4,15 @@
 // (WG) owns a tile of BR rows x BC columns, forms the exponent
 //     t_ij = log2(e) (u_i + v_j + w - C_ij / gamma)   (in FP64)
 // takes 2^t in FP32 and accumulates FP64 row and column partial sums of the
-// tile (B(z)'s row sums R, column sums Q and total T, Section 2.1).  In
-// `fin_pass` each WG reduces the partials of 64 rows or columns and applies
-// the per-row (per-column) step of the algorithm; the last WG makes the
-// scalar decisions of the iteration (block choice, argmin, stopping) for the
-// next pass.  No host round trip per iteration.
+// tile (B(z)'s row sums R, column sums Q and total T, Section 2.1), formed
+// relative to the tile's binary shift K (kept per tile) and stored scaled by
+// 2^K while that stays in the normal FP64 range; a tile beyond it stores them
+// relative to 2^K and marks the pass wide.  In `fin_pass` each WG sums the
+// partials of 64 rows or columns (in a wide pass exactly, as mantissa and
+// exponent, so that sums beyond the FP64 range keep their logarithm) and
+// applies the per-row (per-column) step of the algorithm; the last WG makes
+// the scalar decisions of the iteration (block choice, argmin, stopping) for
+// the next pass.  No host round trip per iteration.
 //
 // The FP64 rounding passes (`round_pass`) use the same tile/strip scheme with
 // an FP64 exponential and FP64 accumulation.
@@ -37,7 +41,7 @@ __device__ void gather_strips(const double* part, int nstrips, double (&tot)[kSc
     block_sum<kScal>(tot, lds);
 }
 
-__device__ void decide(const PassArgs& A, Ctl& cs, double* lds /* >= 17 */) {
+__device__ void decide(const PassArgs& A, Ctl& cs, double* lds /* >= 17 */, bool wide) {
     double Rs[kScal], Cs[kScal];
     const bool rows = A.phase != PH_SK_COL;
     const bool cols = A.phase != PH_SK_ROW;
@@ -47,33 +51,42 @@ __device__ void decide(const PassArgs& A, Ctl& cs, double* lds /* >= 17 */) {
         // lanes (one DPP row each) take one slot each: group k, lane g sums
         // slot k % 8 of side k / 8 (row blocks, column blocks) over blocks g,
         // g + 16, ..., loading 8 blocks per batch, and the row is then reduced
-        // in 4 DPP steps.  A Sinkhorn pass has one side (groups 0..7); its
-        // group 1 merges the blocks' (max, sum of exp) pairs of slots 1 and 2:
-        // running maximum per lane, then the row maximum, then one rescaling
-        // exponential per lane before the row sum.
+        // in 4 DPP steps.  A Sinkhorn pass has one side (groups 0..7).  One
+        // group merges pairs (x, y) whose value is y scaled by x: in a
+        // Sinkhorn pass group 1, the blocks' (max, sum of exp) of slots 1 and
+        // 2 (y e^x); in a wide ASPOT pass group 0, the total's share and its
+        // binary exponent, slots 0 and 6 (y 2^x, rescaled exactly).  Running
+        // maximum of x per lane, then the row maximum, then one rescaling per
+        // lane before the row sum.
         const int tid = threadIdx.x, k = tid >> 4, g = tid & 15;
         const int side = sk ? (rows ? 0 : 1) : (k >> 3);
         const int slot = k & 7;
-        const bool pair = sk && slot == 1;
+        const bool pair = sk ? slot == 1 : (wide && side == 0 && slot == 0);
+        const int xs = pair ? (sk ? 1 : 6) : slot, ys = sk ? 2 : 0;
         const int nside = (sk && k >= 8) ? 0 : (side == 0 ? (rows ? A.nrb : 0) : (cols ? A.ncb : 0));
         const double* base = side == 0 ? A.ws.rowscal : A.ws.colscal;
+        // y scaled by x - top (x <= top): e^(x - top) or 2^(x - top)
+        auto scaled = [&](double y, double x, double top) -> double {
+            if (sk) return x == -INFINITY ? 0.0 : y * exp(x - top);
+            return ldexp(y, (int)fmax(x - top, -4096.0));
+        };
         double v = 0.0, m = -INFINITY;
         for (int b0 = g; b0 < nside; b0 += 16 * 8) {
             double x[8], y[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int b = b0 + 16 * u;
-                x[u] = b < nside ? ld_agent(&base[(int64_t)b * kScal + slot]) : (pair ? -INFINITY : 0.0);
-                y[u] = (pair && b < nside) ? ld_agent(&base[(int64_t)b * kScal + 2]) : 0.0;
+                x[u] = b < nside ? ld_agent(&base[(int64_t)b * kScal + xs]) : (pair ? -INFINITY : 0.0);
+                y[u] = (pair && b < nside) ? ld_agent(&base[(int64_t)b * kScal + ys]) : 0.0;
             }
             if (pair) {
                 double bm = m;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) bm = fmax(bm, x[u]);
                 if (bm != -INFINITY) {
-                    double acc = m == -INFINITY ? 0.0 : v * exp(m - bm);
+                    double acc = scaled(v, m, bm);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) acc += x[u] == -INFINITY ? 0.0 : y[u] * exp(x[u] - bm);
+                    for (int u = 0; u < 8; ++u) acc += scaled(y[u], x[u], bm);
                     m = bm;
                     v = acc;
                 }
@@ -82,14 +95,13 @@ __device__ void decide(const PassArgs& A, Ctl& cs, double* lds /* >= 17 */) {
                 for (int u = 0; u < 8; ++u) v += x[u];
             }
         }
-        double M = -INFINITY;
-        if (sk) {
-            M = m;
+        double M = m;
+        if (sk || wide) {
             M = fmax(M, dpp_d<kQuadX1>(M, M));
             M = fmax(M, dpp_d<kQuadX2>(M, M));
             M = fmax(M, dpp_d<kHalfMirror>(M, M));
             M = fmax(M, dpp_d<kMirror>(M, M));
-            if (pair) v = (m == -INFINITY) ? 0.0 : v * exp(m - M);
+            if (pair) v = M == -INFINITY ? 0.0 : scaled(v, m, M);
         }
         v += dpp_d<kQuadX1>(v, 0.0);
         v += dpp_d<kQuadX2>(v, 0.0);
@@ -106,10 +118,13 @@ __device__ void decide(const PassArgs& A, Ctl& cs, double* lds /* >= 17 */) {
         if (sk) {
             if (rows) { Rs[1] = lds[16]; Rs[2] = lds[1]; }
             else { Cs[1] = lds[16]; Cs[2] = lds[1]; }
+        } else {
+            Rs[6] = wide ? lds[16] : 0.0;    // T = Rs[0] 2^Rs[6]
         }
     }
     if (threadIdx.x == 0) {
         decide_logic(A, cs, Rs, Cs);
+        cs.wide = 0;                 // the next tile pass marks itself
         // the host polls this flag between chunks of iterations (system
         // scope: host memory)
         if (cs.done && A.host_done) __hip_atomic_store(A.host_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -173,6 +188,10 @@ __device__ __forceinline__ int tile_index() {
 constexpr int kMaxBR = 256;
 typedef float f32x4 __attribute__((ext_vector_type(4)));   // 16-byte vector of the tile loads
 constexpr int kMaxBC = 512;
+constexpr int kShiftMax = 1 << 29;   // |tile shift| bound (log2 units), as the duals' clamp
+// Within +-kWideShift every nonzero scaled partial (>= 2^-149 2^K, <= 2^62
+// 2^K) and every sum of them stays in the normal FP64 range.
+constexpr int kWideShift = 800;
 
 template <int KIND, int PHASE>
 __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
@@ -297,6 +316,9 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     // A level outside [2^-60, 2^60] (far-apart points, tiny or huge duals at
     // extrapolated ASPOT points) moves the shift and sweeps again; the shift
     // is kept for the tile's next pass, so a far tile re-sweeps once per solve.
+    // Within the normal window of the shift the partials are written scaled
+    // by 2^K; beyond it they are written relative to 2^K, the pass is marked
+    // wide, and the finalising pass reads the shift beside them.
     double colacc[VW];
 
     // terms of one row: returns the row's lane partial and adds to col32
@@ -461,7 +483,10 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         return l;
     };
 
-    double scale_d = ldexp(1.0, K);
+    // partials are stored times 2^K while |K| <= kWideShift (normal FP64
+    // values), else as computed (relative to 2^K)
+    auto out_scale = [](int k) { return (k > kWideShift || k < -kWideShift) ? 1.0 : ldexp(1.0, k); };
+    double scale_d = out_scale(K);
     double lvl = block_level(sweep(true, scale_d));
     const double kHi = 1.152921504606846976e18;   // 2^60
     const double kLo = 8.673617379884035472e-19;  // 2^-60
@@ -478,16 +503,20 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
             __syncthreads();
             delta = isfinite(mx) ? (int)floor(mx) : 0;
         }
-        delta = max(-2000 - K, min(2000 - K, delta));
+        delta = max(-kShiftMax - K, min(kShiftMax - K, delta));
         if (delta != 0) {
             for (int r = tid; r < rows; r += kThreads) s_a[r] -= (double)delta;
             K += delta;
             __syncthreads();
-            scale_d = ldexp(1.0, K);
+            scale_d = out_scale(K);
             sweep(false, scale_d);
             if (tid == 0) A.ws.tshift[tile] = K;
         }
     }
+    // a shift beyond +-kWideShift can take the scaled partials or their sums
+    // out of the normal FP64 range: the finalising pass then combines them
+    // as mantissa and exponent
+    if (tid == 0 && (K > kWideShift || K < -kWideShift)) A.ws.ctl->wide = 1;
     if (COLS) {
 #pragma unroll
         for (int k = 0; k < VW; ++k) s_col[wave * (64 * VW) + lane * VW + k] = colacc[k];
@@ -509,11 +538,58 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
 // decisions.
 // ---------------------------------------------------------------------------
 constexpr int kFinBlock = 64;
+constexpr int kNoExp = -(1 << 30);   // exponent of a sum with no positive finite term
+
+// acc 2^e += v 2^K, exactly (a change of e only rescales acc by a power of
+// two): e follows the largest term, so terms far below it vanish and nothing
+// overflows.  Zero adds nothing; a non-finite v propagates.  Branch-free, so
+// that a batch of partial loads stays in flight ahead of the arithmetic.
+__device__ __forceinline__ void add_shifted(double& acc, int& e, double v, int K) {
+    const bool pos = v > 0.0 && v <= 1.7976931348623157e308;
+    const int ev = pos ? K + ilogb(pos ? v : 1.0) : kNoExp;
+    const int en = max(e, ev);
+    acc = ldexp(acc, e - en) + (pos ? ldexp(v, K - en) : v);
+    e = en;
+}
+
+// Plain sum of this thread's strips q, q + 4, ... < cnt of one row or column
+// (partial of strip x at p[x ps]), in strip order.  Loads go out 4 strips at
+// a time (indices clamped into range) before any arithmetic; the first batch
+// is straight-line code, since a loop header waits for every load in flight.
+__device__ __forceinline__ double sum_strips(const double* p, int64_t ps, int q, int cnt) {
+    double acc = 0.0;
+    auto batch = [&](int x0) __attribute__((always_inline)) {
+        double pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pv[u] = p[(int64_t)min(x0 + 4 * u, cnt - 1) * ps];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += x0 + 4 * u < cnt ? pv[u] : 0.0;   // (sums are >= 0: + 0 is exact)
+    };
+    batch(q);
+    for (int x0 = q + 4 * 4; x0 < cnt; x0 += 4 * 4) batch(x0);
+    return acc;
+}
+
+// The same sum in a wide pass, exactly, as acc 2^ex: a partial whose tile
+// shift K lies beyond +-kWideShift is relative to 2^K, the others are stored
+// scaled.  A sum with no positive or non-finite term keeps ex = kNoExp.
+// (out of line: only a wide pass runs it)
+__device__ __noinline__ void sum_strips_exact(const double* p, int64_t ps, const int32_t* ks, int64_t kst, int q,
+                                              int cnt, double& acc, int& ex) {
+    acc = 0.0;
+    ex = kNoExp;
+    for (int x = q; x < cnt; x += 4) {
+        const int K = ks[(int64_t)x * kst];
+        add_shifted(acc, ex, p[(int64_t)x * ps], (K > kWideShift || K < -kWideShift) ? K : 0);
+    }
+}
 
 template <int PHASE>
 __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
     __shared__ double s_part[4][kFinBlock];
+    __shared__ int s_pe[4][kFinBlock];
     __shared__ double s_v[kFinBlock];
+    __shared__ int s_ve[kFinBlock];
     __shared__ double s_red[4 * 2 * kScal];
     __shared__ int s_last;
     __shared__ Ctl s_ctl;                              // snapshot of the control block
@@ -526,34 +602,54 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
     const int cb = rows_pass ? blk - A.nrb : blk;      // column block index
     const int base = is_row ? blk * kFinBlock : cb * kFinBlock;
     const int len = min(kFinBlock, (is_row ? A.n : A.m) - base);
-    // loads first, all in one batch: the control block, the tile partials (4
-    // threads per row or column, each a quarter of the strips) and the state
-    // of the step
+    // loads first, in one batch: the control block, the state of the step,
+    // then the tile partials (4 threads per row or column, each a quarter of
+    // the strips); a wide pass reloads the partials with their tiles' shifts
     const uint64_t cw = tid < kCtlWords ? reinterpret_cast<const uint64_t*>(A.ws.ctl)[tid] : 0;
     // (indices clamped into range: no divergent loads)
-    const int l = tid & (kFinBlock - 1), q = tid / kFinBlock;
-    double acc = 0.0;
-    {
-        const int lc = min(l, len - 1);
-        if (is_row) {
-            const double* p = (const double*)A.ws.rowpart + base + lc;
-#pragma unroll 4
-            for (int x = q; x < A.nx; x += 4) acc += p[(int64_t)x * A.n];
-        } else {
-            const double* p = (const double*)A.ws.colpart + base + lc;
-#pragma unroll 4
-            for (int y = q; y < A.ny; y += 4) acc += p[(int64_t)y * A.m];
-        }
-        if (l >= len) acc = 0.0;
-    }
     const StepPre pre = load_step<PHASE>(A, is_row, base + min(tid, len - 1));
+    const int l = tid & (kFinBlock - 1), q = tid / kFinBlock;
+    const int lc = min(l, len - 1), idx = base + lc;
+    double acc = is_row ? sum_strips((const double*)A.ws.rowpart + idx, A.n, q, A.nx)
+                        : sum_strips((const double*)A.ws.colpart + idx, A.m, q, A.ny);
     if (tid < kCtlWords) reinterpret_cast<uint64_t*>(&s_ctl)[tid] = cw;
-    s_part[q][l] = acc;
+    s_part[q][l] = l < len ? acc : 0.0;
     __syncthreads();
     const Ctl& c = s_ctl;
     if (c.done) return;              // (uniform: every thread reads the same word)
-    // the partials combined in a fixed order
-    if (tid < kFinBlock) s_v[tid] = (s_part[0][tid] + s_part[1][tid]) + (s_part[2][tid] + s_part[3][tid]);
+    // a wide pass: the exact sums as acc 2^ex (partial x of row idx: tile
+    // (idx / br, x); partial y of column idx: tile (y, idx / bc))
+    const bool wide = c.wide != 0;
+    if (wide) {
+        int ex;
+        if (is_row)
+            sum_strips_exact((const double*)A.ws.rowpart + idx, A.n, A.ws.tshift + (int64_t)(idx / A.br) * A.nx, 1,
+                             q, A.nx, acc, ex);
+        else
+            sum_strips_exact((const double*)A.ws.colpart + idx, A.m, A.ws.tshift + idx / A.bc, A.nx, q, A.ny, acc,
+                             ex);
+        s_part[q][l] = l < len ? acc : 0.0;
+        s_pe[q][l] = l < len ? ex : kNoExp;
+        __syncthreads();
+    }
+    // the quarters combined in a fixed order, on the largest exponent (the
+    // rescalings are exact: in the FP64 range these are the plain sums)
+    if (tid < kFinBlock) {
+        int e = 0;
+        double v;
+        if (!wide) {
+            v = (s_part[0][tid] + s_part[1][tid]) + (s_part[2][tid] + s_part[3][tid]);
+        } else {
+            e = max(max(s_pe[0][tid], s_pe[1][tid]), max(s_pe[2][tid], s_pe[3][tid]));
+            v = (ldexp(s_part[0][tid], s_pe[0][tid] - e) + ldexp(s_part[1][tid], s_pe[1][tid] - e)) +
+                (ldexp(s_part[2][tid], s_pe[2][tid] - e) + ldexp(s_part[3][tid], s_pe[3][tid] - e));
+            if (e == kNoExp) e = 0;
+        }
+        // (the Sinkhorn steps take the value itself)
+        const bool skp = PHASE == PH_SK_ROW || PHASE == PH_SK_COL;
+        s_v[tid] = skp ? ldexp(v, e) : v;
+        s_ve[tid] = skp ? 0 : e;
+    }
     __syncthreads();
     double* out = (is_row ? A.ws.rowscal + (int64_t)blk * kScal : A.ws.colscal + (int64_t)cb * kScal);
     if constexpr (PHASE == PH_SK_ROW) {
@@ -564,10 +660,23 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
         double sums[kScal];
 #pragma unroll
         for (int k = 0; k < kScal; ++k) sums[k] = 0.0;
-        if (tid < len) aspot_step<PHASE>(A, is_row, base + tid, s_v[tid], pre, sums);
+        // slot 0 (the block's share of T) is carried as sums[0] 2^eref, eref
+        // the largest exponent of the block's row sums (slot 6)
+        double eref = 0.0;
+        if (tid < kFinBlock) {       // wave 0: the block's rows or columns
+            const double Rm = s_v[tid];
+            const int Re = s_ve[tid];
+            if (wide) {
+                const bool pos = tid < len && Rm > 0.0 && Rm <= 1.7976931348623157e308;
+                eref = wave_max(pos ? (double)(Re + ilogb(pos ? Rm : 1.0)) : -INFINITY);
+                if (!(eref > -INFINITY)) eref = 0.0;
+            }
+            if (tid < len)
+                aspot_step<PHASE>(A, is_row, base + tid, Rm, Re, ldexp(Rm, Re - (int)eref), pre, sums);
+        }
         block_sum<kScal>(sums, s_red);
         if (tid == 0)
-            for (int k = 0; k < kScal; ++k) st_agent(&out[k], sums[k]);
+            for (int k = 0; k < kScal; ++k) st_agent(&out[k], k == 6 ? (is_row ? eref : 0.0) : sums[k]);
     }
     // arrival: the last block decides
     wait_stores();
@@ -576,7 +685,7 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
     if (tid == 0) s_last = (atomicAdd(&A.ws.glob[0], 1) == total - 1);
     __syncthreads();
     if (s_last) {
-        decide(A, s_ctl, s_red);
+        decide(A, s_ctl, s_red, wide);
         if (tid == 0) st_agent(&A.ws.glob[0], 0);
     }
 }

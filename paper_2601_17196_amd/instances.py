@@ -175,6 +175,20 @@ def c2(k: int = 0, n: int = 4096, dense: bool = True) -> Instance:
     return _finish(x, y, r, c, 0.9, 1e-2, f"c2[{k}] n=m={n} 3-D clusters+outliers", dense)
 
 
+def tight_clusters(n: int = 512, k: int = 0, sigma: float = 0.01) -> Instance:
+    """The C2 recipe with tighter clusters (sigma = 0.01 by default): many
+    pairs cost almost nothing, so the cold start's total T is large and the
+    first step of a long-step rule moves w by thousands (statistics far below
+    the FP64 range at the next point).  n = m, uniform masses 1/1, s = 0.9."""
+    g = _rng(7, k)
+    centres = g.uniform(0.0, 1.0, size=(8, 3))
+    x = _cluster_cloud(g, centres, n, sigma, 0.10)
+    y = _cluster_cloud(g, centres, n, sigma, 0.10)
+    r = np.full(n, 1.0 / n)
+    c = np.full(n, 1.0 / n)
+    return _finish(x, y, r, c, 0.9, 1e-2, f"tight[{k}] n=m={n} 3-D clusters sigma={sigma}")
+
+
 def c3(k: int = 0, n: int = 20000, eps: float = 1e-2, dense: bool = True) -> Instance:
     """n = m = 20000, 2-D: source is a 5-component equal-weight Gaussian
     mixture (centres ~ U[0,1]^2, sigma = 0.05); target is the same mixture
