@@ -311,13 +311,22 @@ __device__ bool member_pass(Member& M, BShared& S) {
             const double mx = member_max_exponent<KIND>(M, S, G2) - (double)K;
             delta = isfinite(mx) ? (int)floor(mx) : 0;
         }
-        delta = max(-2000 - K, min(2000 - K, delta));
+        // (a lone member of an ASPOT pass may go as far as the duals' clamp:
+        // its sums are then kept relative to 2^K below)
+        const int kmax = (M.G == 1 && ROWS && COLS) ? (1 << 29) : 2000;
+        delta = max(-kmax - K, min(kmax - K, delta));
         if (delta != 0) {
             K += delta;
             lvl = member_sweep<KIND, VW, KC>(M, S, G2, (double)K, b, colacc);
         }
     }
-    const double scale_d = ldexp(1.0, K);
+    // Sums are scaled by 2^K while |K| <= 800 (normal FP64 values); a lone
+    // member of an ASPOT pass beyond that keeps them relative to 2^K and
+    // hands the steps and the decisions the exponent Ke (a group's members
+    // exchange plain FP64 sums).
+    const bool rel = M.G == 1 && ROWS && COLS && (K > 800 || K < -800);
+    const int Ke = rel ? K : 0;
+    const double scale_d = rel ? 1.0 : ldexp(1.0, K);
     if (COLS) {
 #pragma unroll
         for (int k = 0; k < KC; ++k)
@@ -378,8 +387,8 @@ __device__ bool member_pass(Member& M, BShared& S) {
     } else {
         // rows and columns side by side (one element per thread at the sizes of a batch)
         for (int k = tid; k < nr + m; k += kBThreads) {
-            if (k < nr) aspot_step<PH>(A, true, r0 + k, S.R[k], 0, S.R[k], load_step<PH>(A, true, r0 + k), Rs);
-            else aspot_step<PH>(A, false, k - nr, S.Q[k - nr], 0, 0.0, load_step<PH>(A, false, k - nr), Cs);
+            if (k < nr) aspot_step<PH>(A, true, r0 + k, S.R[k], Ke, S.R[k], load_step<PH>(A, true, r0 + k), Rs);
+            else aspot_step<PH>(A, false, k - nr, S.Q[k - nr], Ke, 0.0, load_step<PH>(A, false, k - nr), Cs);
         }
         block_sum<kScal, kBWaves>(Rs, S.red);
         block_sum<kScal, kBWaves>(Cs, S.red);
@@ -407,6 +416,7 @@ __device__ bool member_pass(Member& M, BShared& S) {
     }
     if (tid == 0) {
         A.phase = PH;
+        if (ROWS && COLS) Rs[6] = (double)Ke;      // T = Rs[0] 2^Ke
         decide_logic(A, S.ctl, Rs, Cs);
     }
     __syncthreads();

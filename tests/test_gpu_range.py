@@ -74,3 +74,40 @@ def test_solve_converges_like_the_oracle():
         assert rel(res["cost"], ref.rounded["cost"]) <= 1e-6
     else:
         assert abs(res["cost"] - ref.rounded["cost"]) <= inst.eps
+
+
+def _batched(inst, **kw):
+    import torch
+
+    from paper_2601_17196_amd import pot
+    d = pot.to_device_instance(inst, "cuda:0", kind="f32")
+    prob = dict(r=d["r"], c=d["c"], s=d["s"], C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0)
+    st, res, _ = pot.solve_batched([prob], inst.eps, algo=pot.ASPOT, step_rule=1, **kw)
+    torch.cuda.synchronize()
+    return st, res[0]
+
+
+def test_batched_lone_member_follows_the_single_solve():
+    """pot_solve_batched with the instance in one workgroup (member_elems =
+    n m) carries the same range: it converges with the single solve."""
+    inst = _inst()
+    print("range: batched, one member", flush=True)
+    st, r = _batched(inst, member_elems=512 * 512)
+    one = gpu_solve(inst, "f32", "aspot", step_rule=1).result
+    assert st == 0 and r["status"] == 0
+    print(f"iterations batched {r['iters']} single {one['iters']}", flush=True)
+    if r["iters"] == one["iters"]:
+        assert rel(r["cost"], one["cost"]) <= 1e-6
+    else:
+        assert abs(r["cost"] - one["cost"]) <= inst.eps
+
+
+def test_batched_group_reports_the_range_limit():
+    """Split over a group of members (row shares), the batched path keeps
+    plain FP64 sums: it reports the unrepresentable statistics instead of
+    continuing."""
+    from paper_2601_17196_amd import pot
+    inst = _inst()
+    print("range: batched, group of members", flush=True)
+    st, r = _batched(inst, member_elems=1 << 15)
+    assert r["status"] == pot.ERR_NUMERIC
