@@ -25,10 +25,11 @@ def _inst():
     return I.tight_clusters(512, 0)
 
 
-def test_first_iterations_follow_the_oracle():
+@pytest.mark.parametrize("kind", ["f32", "points"])
+def test_first_iterations_follow_the_oracle(kind):
     inst = _inst()
-    print("range: tight clusters n=512, step_rule=1, 40 iterations", flush=True)
-    C = oracle_cost_matrix(inst, "f32")
+    print(f"range: tight clusters n=512, {kind}, step_rule=1, 40 iterations", flush=True)
+    C = oracle_cost_matrix(inst, kind)
     gam, tol, M, rt, ct_ = O.setup(inst.r, inst.c, inst.s, inst.eps, cmax=1.0)
     u, v, w, k, E, st, tr = O.aspot(C, gam, tol, rt, ct_, inst.s, M, max_iter=N_TRACE, step_rule=1,
                                     trace=True, trace_ztil=True)
@@ -37,7 +38,7 @@ def test_first_iterations_follow_the_oracle():
     # below e^(w + max u + max v) < 2^-1074
     zt = tr.ztil[1]
     assert zt[-1] + zt[:512].max() + zt[512:-1].max() < -1100.0
-    out = gpu_solve(inst, "f32", "aspot", trace_cap=N_TRACE + 8, step_rule=1, max_iter=N_TRACE)
+    out = gpu_solve(inst, kind, "aspot", trace_cap=N_TRACE + 8, step_rule=1, max_iter=N_TRACE)
     from paper_2601_17196_amd import pot
     assert out.status == pot.ERR_NO_CONVERGENCE, pot.last_error()
     res = out.result
