@@ -573,9 +573,10 @@ __device__ __forceinline__ double sum_strips(const double* p, int64_t ps, int q,
 // The same sum in a wide pass, exactly, as acc 2^ex: a partial whose tile
 // shift K lies beyond +-kWideShift is relative to 2^K, the others are stored
 // scaled.  A sum with no positive or non-finite term keeps ex = kNoExp.
-// (out of line: only a wide pass runs it)
-__device__ __noinline__ void sum_strips_exact(const double* p, int64_t ps, const int32_t* ks, int64_t kst, int q,
-                                              int cnt, double& acc, int& ex) {
+// (Inline: out of line, its reference arguments would give every finalising
+// launch a scratch segment.)
+__device__ __forceinline__ void sum_strips_exact(const double* p, int64_t ps, const int32_t* ks, int64_t kst, int q,
+                                                 int cnt, double& acc, int& ex) {
     acc = 0.0;
     ex = kNoExp;
     for (int x = q; x < cnt; x += 4) {
