@@ -176,10 +176,11 @@ def c2(k: int = 0, n: int = 4096, dense: bool = True) -> Instance:
 
 
 def tight_clusters(n: int = 512, k: int = 0, sigma: float = 0.01) -> Instance:
-    """The C2 recipe with tighter clusters (sigma = 0.01 by default): many
-    pairs cost almost nothing, so the cold start's total T is large and the
-    first step of a long-step rule moves w by thousands (statistics far below
-    the FP64 range at the next point).  n = m, uniform masses 1/1, s = 0.9."""
+    """The recipe of c2() (3-D, 8 clusters, 10 % outliers) with tighter
+    clusters (sigma = 0.01 by default): many pairs cost almost nothing, so
+    the cold start's total T is large and the first step of a long-step rule
+    moves w by thousands (statistics far below the FP64 range at the next
+    point).  n = m, uniform masses 1/1, s = 0.9."""
     g = _rng(7, k)
     centres = g.uniform(0.0, 1.0, size=(8, 3))
     x = _cluster_cloud(g, centres, n, sigma, 0.10)
