@@ -253,8 +253,9 @@ def main():
                          "solve and 20 timed statistics passes of the default workload; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the solver has no multi-GPU path in this build "
-              "(a row-sharded design is described with the library)", file=sys.stderr)
+        print("bench.py runs on one GPU: the solver has no multi-GPU path (batches would shard by "
+              "instance, one instance by rows of C with one all-reduce of m + 3 values per pass)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
