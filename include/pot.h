@@ -52,7 +52,11 @@ typedef enum {
     POT_OK = 0,
     POT_ERR_INVALID_ARG = 1,     /* bad sizes, masses, eps, pointers or options */
     POT_ERR_NO_CONVERGENCE = 2,  /* max_iter reached; the rounded plan is still in U(r,c,s) */
-    POT_ERR_NUMERIC = 3,         /* a non-finite statistic (overflow of an FP32 sum) */
+    POT_ERR_NUMERIC = 3,         /* a statistic overflowed the FP64 range, or is not a number.
+                                    Sums far below that range are carried as mantissa and
+                                    exponent; pot_solve_batched does so only for an instance
+                                    held by one workgroup (see member_elems): split over a
+                                    group, one leaving the FP64 range is also this error */
     POT_ERR_DEVICE = 4,          /* a HIP runtime call failed */
     POT_ERR_WORKSPACE = 5,       /* workspace too small or misaligned (needs 256 B alignment) */
     POT_ERR_UNSUPPORTED = 6      /* option combination not implemented */
