@@ -52,6 +52,11 @@ struct BShared {
     double R[kBMax];         // row sums of the member's rows (FP64)
     double lR[kBMax];        // their logs (start pass only; exact even where R underflows)
     double Q[kBMax];         // column sums (FP64)
+    // the state an ASPOT step reads, kept on chip: the duals at the point of
+    // the pass (written by the pass's prologue) and the smoothed masses with
+    // their logs (written once by the setup)
+    double xr[kBMax], xc[kBMax];
+    double rt[kBMax], lrt[kBMax], ct[kBMax], lct[kBMax];
     double colw[kBWaves][kBMax];   // per-wave column partials
     double red[64];
     double lvl[kBWaves];
@@ -281,11 +286,15 @@ __device__ bool member_pass(Member& M, BShared& S) {
     for (int r = tid; r < nr; r += kBThreads) {
         const int i = r0 + r;
         const Cand q = load_cand<PH>(A, RV, 0, i);
-        S.a[r] = fmin(fmax((eval_point<PH>(A, c, RV, q, 0, i, true) + wp) * kLog2e, -kClamp), kClamp);
+        const double x = eval_point<PH>(A, c, RV, q, 0, i, true);
+        S.xr[r] = x;
+        S.a[r] = fmin(fmax((x + wp) * kLog2e, -kClamp), kClamp);
     }
     for (int j = tid; j < m; j += kBThreads) {
         const Cand q = load_cand<PH>(A, CV, 1, j);
-        S.b[j] = fmin(fmax(eval_point<PH>(A, c, CV, q, 1, j, true) * kLog2e, -kClamp), kClamp);
+        const double x = eval_point<PH>(A, c, CV, q, 1, j, true);
+        S.xc[j] = x;
+        S.b[j] = fmin(fmax(x * kLog2e, -kClamp), kClamp);
     }
     __syncthreads();
 
@@ -385,10 +394,17 @@ __device__ bool member_pass(Member& M, BShared& S) {
         block_sum<1, kBWaves>(v, S.red);
         Cs[1] = mx; Cs[2] = se; Cs[7] = v[0];
     } else {
-        // rows and columns side by side (one element per thread at the sizes of a batch)
+        // rows and columns side by side (one element per thread at the sizes
+        // of a batch); the state comes from LDS (the point's duals, the masses)
         for (int k = tid; k < nr + m; k += kBThreads) {
-            if (k < nr) aspot_step<PH>(A, true, r0 + k, S.R[k], Ke, S.R[k], load_step<PH>(A, true, r0 + k), Rs);
-            else aspot_step<PH>(A, false, k - nr, S.Q[k - nr], Ke, 0.0, load_step<PH>(A, false, k - nr), Cs);
+            if (k < nr) {
+                const StepPre p = {S.xr[k], S.rt[k], S.lrt[k], 0.0};
+                aspot_step<PH>(A, true, r0 + k, S.R[k], Ke, S.R[k], p, Rs);
+            } else {
+                const int j = k - nr;
+                const StepPre p = {S.xc[j], S.ct[j], S.lct[j], 0.0};
+                aspot_step<PH>(A, false, j, S.Q[j], Ke, 0.0, p, Cs);
+            }
         }
         block_sum<kScal, kBWaves>(Rs, S.red);
         block_sum<kScal, kBWaves>(Cs, S.red);
@@ -472,6 +488,8 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
         if (i >= M.r0 && i < M.r0 + M.nr) {
             w.rt[i] = x;
             w.lrt[i] = log(x);
+            S.rt[i - M.r0] = x;
+            S.lrt[i - M.r0] = w.lrt[i];
             if (B.algo == POT_SINKHORN) w.uchk0[i] = 0.0;
         }
         u[2] += x > 0.0 ? 0.0 : 1.0;
@@ -481,6 +499,8 @@ __device__ int member_setup(Member& M, BShared& S, const BArgs& B) {
         const double x = smooth_mass(D.c[j], et, m);
         w.ct[j] = x;
         w.lct[j] = log(x);
+        S.ct[j] = x;
+        S.lct[j] = w.lct[j];
         if (B.algo == POT_SINKHORN) w.vz[j] = 0.0;
         u[2] += x > 0.0 ? 0.0 : 1.0;
         u[1] += x;
