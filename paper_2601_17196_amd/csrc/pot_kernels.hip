@@ -206,12 +206,12 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     __shared__ double s_x[PTS ? kMaxBR * 3 : 1];   // points: source coordinates - tile origin (FP64)
     __shared__ double s_y[PTS ? 256 * 3 : 1];      // points (BC = 256): 2 G (target coordinates - tile origin)
     __shared__ double s_lvl[4];
-    // one 16 KB buffer reused by the phases of the kernel:
-    //   sweep:     per-lane row partials of a 64-row chunk, float [4][16][64]
-    //   columns:   column partials of the 4 waves, double [4][BC]
+    // per-lane row partials of a 64-row chunk, float [4][16][64]
     __shared__ __align__(16) double s_buf[2048];
     float (*s_rowp)[16][64] = reinterpret_cast<float (*)[16][64]>(s_buf);
-    double* s_col = s_buf;                 // [4][bc]
+    // column partials of the 4 waves, double [4][BC] (an area of their own,
+    // so that the kernel's tail needs one barrier)
+    __shared__ double s_col[4 * kMaxBC];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = tile_index();
@@ -353,7 +353,9 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     };
 
     // reduce the per-lane row partials of a 64-row chunk; write them; level
-    auto emit_rows = [&](int c0, double scale_d, double& lvl) __attribute__((always_inline)) {
+    // (the last chunk skips the trailing barrier: what follows writes other
+    // LDS areas, and a re-sweep synchronises before its first chunk)
+    auto emit_rows = [&](int c0, double scale_d, double& lvl, bool last) __attribute__((always_inline)) {
         __syncthreads();
         const int rl = tid >> 2, q = tid & 3;          // row of the chunk, quarter of the lanes
         const int wv = rl & 3, slot = rl >> 2;         // row rl = wave wv's slot-th row
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
             lvl = fmax(lvl, sacc);                     // (NaN sums reach the finalisers' check)
             if (ROWS && q == 0) ((double*)A.ws.rowpart)[(int64_t)tx * A.n + i0 + r] = sacc * scale_d;
         }
-        __syncthreads();
+        if (!last) __syncthreads();
     };
 
     auto sweep = [&](bool use_pre, double scale_d) __attribute__((always_inline)) -> double {
@@ -444,7 +446,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
                     s_rowp[wave][slot][lane] = rs;
                 }
             }
-            emit_rows(c0, scale_d, lvl);
+            emit_rows(c0, scale_d, lvl, c0 + 64 >= rows);
         }
         if (COLS) {
             // the level also covers this thread's column sums
@@ -474,23 +476,28 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
         return mx;
     };
 
-    auto block_level = [&](double v) -> double {
+    // the waves' column partials and levels into LDS, one barrier, the
+    // tile's level
+    auto stage = [&](double v) -> double {
+        if (COLS) {
+#pragma unroll
+            for (int k = 0; k < VW; ++k) s_col[wave * (64 * VW) + lane * VW + k] = colacc[k];
+        }
         v = wave_max(v);
         if (lane == 0) s_lvl[wave] = v;
         __syncthreads();
-        double l = fmax(fmax(s_lvl[0], s_lvl[1]), fmax(s_lvl[2], s_lvl[3]));
-        __syncthreads();
-        return l;
+        return fmax(fmax(s_lvl[0], s_lvl[1]), fmax(s_lvl[2], s_lvl[3]));
     };
 
     // partials are stored times 2^K while |K| <= kWideShift (normal FP64
     // values), else as computed (relative to 2^K)
     auto out_scale = [](int k) { return (k > kWideShift || k < -kWideShift) ? 1.0 : ldexp(1.0, k); };
     double scale_d = out_scale(K);
-    double lvl = block_level(sweep(true, scale_d));
+    double lvl = stage(sweep(true, scale_d));
     const double kHi = 1.152921504606846976e18;   // 2^60
     const double kLo = 8.673617379884035472e-19;  // 2^-60
     if (!(lvl <= kHi && lvl >= kLo)) {
+        __syncthreads();                   // every wave has read the levels
         int delta;
         if (lvl > 0.0 && lvl < INFINITY) delta = ilogb(lvl);
         else {
@@ -509,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
             K += delta;
             __syncthreads();
             scale_d = out_scale(K);
-            sweep(false, scale_d);
+            stage(sweep(false, scale_d));  // the new column partials
             if (tid == 0) A.ws.tshift[tile] = K;
         }
     }
@@ -518,9 +525,6 @@ __global__ __launch_bounds__(kThreads) void stats_pass(PassArgs A) {
     // as mantissa and exponent
     if (tid == 0 && (K > kWideShift || K < -kWideShift)) A.ws.ctl->wide = 1;
     if (COLS) {
-#pragma unroll
-        for (int k = 0; k < VW; ++k) s_col[wave * (64 * VW) + lane * VW + k] = colacc[k];
-        __syncthreads();
         for (int q = tid; q < cols; q += kThreads) {
             const int B = 64 * VW;
             double v = (s_col[q] + s_col[B + q]) + (s_col[2 * B + q] + s_col[3 * B + q]);
