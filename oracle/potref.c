@@ -737,3 +737,100 @@ int potref_round_dense(int n, int m, const double* X, const double* r,
     free(alpha); free(beta); free(pp); free(qq);
     return POTREF_OK;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Checks of a solver's output point (used to judge another solver's       */
+/* result against the definitions, not by the algorithms above).           */
+/* ---------------------------------------------------------------------- */
+/* Stopping error of feasible Sinkhorn (Algorithm 3) at the extended
+   log-scalings a (n+1), b (m+1): |X^ 1 - r^|_1 + |X^T 1 - c^|_1 with
+   X^_ij = exp(a_i + b_j - C^_ij / gamma), C^ = [[C, 0], [0^T, A]],
+   r^ = (r~, |c~|_1 - s), c^ = (c~, |r~|_1 - s).  Every entry is summed
+   directly; no dummy row or column is treated in closed form. */
+double potref_sk_error(int n, int m, const double* C, long ldc, double gamma,
+                       const double* rt, const double* ct, double s, double A,
+                       const double* a, const double* b) {
+    const int n1 = n + 1, m1 = m + 1;
+    const double ig = 1.0 / gamma;
+    double* rows = (double*)malloc(sizeof(double) * (size_t)n1);
+    double* cols = (double*)calloc((size_t)m1, sizeof(double));
+    double rh_d = sum_vec(m, ct) - s, ch_d = sum_vec(n, rt) - s;
+    if (rh_d < 0.0) rh_d = 0.0;
+    if (ch_d < 0.0) ch_d = 0.0;
+#pragma omp parallel
+    {
+        double* cl = (double*)calloc((size_t)m1, sizeof(double));
+#pragma omp for schedule(static)
+        for (int i = 0; i < n1; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < m1; ++j) {
+                double cij = (i < n && j < m) ? C[(long)i * ldc + j] : ((i == n && j == m) ? A : 0.0);
+                double x = exp(a[i] + b[j] - cij * ig);
+                acc += x;
+                cl[j] += x;
+            }
+            rows[i] = acc;
+        }
+#pragma omp critical
+        for (int j = 0; j < m1; ++j) cols[j] += cl[j];
+        free(cl);
+    }
+    double e = 0.0;
+    for (int i = 0; i < n1; ++i) e += fabs(rows[i] - (i < n ? rt[i] : rh_d));
+    for (int j = 0; j < m1; ++j) e += fabs(cols[j] - (j < m ? ct[j] : ch_d));
+    free(rows);
+    free(cols);
+    return e;
+}
+
+/* A plan given in factored form,
+     Xbar_ij = kappa alpha_i exp(f_i + g_j - Cp_ij / gamma) beta_j + lambda p'_i q'_j,
+   evaluated entry by entry: its row sums (rows_out, n), column sums
+   (cols_out, m), out3 = {<Ce, Xbar>, 1^T Xbar 1, min_ij Xbar_ij}.  Cp is the
+   cost inside the exponent, Ce the cost the plan is priced with (they differ
+   when a plan computed on a rounded cost is priced on the exact one). */
+int potref_plan_eval(int n, int m, const double* Cp, long ldp, const double* Ce, long lde,
+                     double gamma, const double* f, const double* g,
+                     const double* alpha, const double* beta, double kappa, double lambda,
+                     const double* pp, const double* qq,
+                     double* rows_out, double* cols_out, double* out3) {
+    const double ig = 1.0 / gamma;
+    double* part = (double*)malloc(sizeof(double) * (size_t)n);
+    double* cols = (double*)calloc((size_t)m, sizeof(double));
+    double mn = INFINITY;
+#pragma omp parallel
+    {
+        double* x = (double*)malloc(sizeof(double) * (size_t)m);
+        double* cx = (double*)malloc(sizeof(double) * (size_t)m);
+        double* cl = (double*)calloc((size_t)m, sizeof(double));
+        double lmn = INFINITY;
+#pragma omp for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            for (int j = 0; j < m; ++j) {
+                double xt = exp(f[i] + g[j] - Cp[(long)i * ldp + j] * ig);
+                double v = kappa * (alpha[i] * xt * beta[j]) + lambda * pp[i] * qq[j];
+                x[j] = v;
+                cx[j] = Ce[(long)i * lde + j] * v;
+                cl[j] += v;
+                if (v < lmn) lmn = v;
+            }
+            rows_out[i] = sum_vec(m, x);
+            part[i] = sum_vec(m, cx);
+        }
+#pragma omp critical
+        {
+            for (int j = 0; j < m; ++j) cols[j] += cl[j];
+            if (lmn < mn) mn = lmn;
+        }
+        free(x);
+        free(cx);
+        free(cl);
+    }
+    for (int j = 0; j < m; ++j) cols_out[j] = cols[j];
+    out3[0] = sum_vec(n, part);
+    out3[1] = sum_vec(n, rows_out);
+    out3[2] = mn;
+    free(part);
+    free(cols);
+    return POTREF_OK;
+}

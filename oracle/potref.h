@@ -138,6 +138,24 @@ int potref_round_dense(int n, int m, const double* X, const double* r,
 /* <C, X> with compensated (Neumaier) summation. */
 double potref_cost(int n, int m, const double* C, long ldc, const double* X);
 
+/* Stopping error of feasible Sinkhorn (Algorithm 3) at extended
+ * log-scalings a (n+1) and b (m+1): |X^ 1 - r^|_1 + |X^T 1 - c^|_1 over the
+ * extended instance built from the smoothed marginals rt, ct and s, with
+ * corner cost A.  Every entry is summed directly. */
+double potref_sk_error(int n, int m, const double* C, long ldc, double gamma,
+                       const double* rt, const double* ct, double s, double A,
+                       const double* a, const double* b);
+
+/* A factored plan Xbar = kappa diag(alpha) X~ diag(beta) + lambda p' q'^T,
+ * X~_ij = exp(f_i + g_j - Cp_ij / gamma), evaluated entry by entry: row
+ * sums (rows_out, n), column sums (cols_out, m) and
+ * out3 = {<Ce, Xbar>, 1^T Xbar 1, min_ij Xbar_ij}. */
+int potref_plan_eval(int n, int m, const double* Cp, long ldp, const double* Ce, long lde,
+                     double gamma, const double* f, const double* g,
+                     const double* alpha, const double* beta, double kappa, double lambda,
+                     const double* pp, const double* qq,
+                     double* rows_out, double* cols_out, double* out3);
+
 /* Number of OpenMP threads the oracle uses. */
 int potref_threads(void);
 

@@ -30,6 +30,8 @@ __all__ = [
     "cost",
     "solve",
     "threads",
+    "sk_error",
+    "plan_eval",
     "set_threads",
     "AspotTrace",
     "OracleSolution",
@@ -109,6 +111,12 @@ def load():
     lib.potref_round_dense.restype = ct.c_int
     lib.potref_cost.argtypes = [ct.c_int, ct.c_int, _D, ct.c_long, _D]
     lib.potref_cost.restype = ct.c_double
+    lib.potref_sk_error.argtypes = [ct.c_int, ct.c_int, _D, ct.c_long, ct.c_double, _D, _D, ct.c_double,
+                                    ct.c_double, _D, _D]
+    lib.potref_sk_error.restype = ct.c_double
+    lib.potref_plan_eval.argtypes = [ct.c_int, ct.c_int, _D, ct.c_long, _D, ct.c_long, ct.c_double, _D, _D,
+                                     _D, _D, ct.c_double, ct.c_double, _D, _D, _D, _D, _D]
+    lib.potref_plan_eval.restype = ct.c_int
     lib.potref_threads.argtypes = []
     lib.potref_threads.restype = ct.c_int
     lib.potref_set_threads.argtypes = [ct.c_int]
@@ -325,6 +333,37 @@ def cost(C, X):
     X = _f64(X)
     n, m = C.shape
     return float(lib.potref_cost(n, m, _p(C), m, _p(X)))
+
+
+def sk_error(C, gamma, rt, ct_, s, A, a, b):
+    """Stopping error of feasible Sinkhorn (Algorithm 3) at the extended
+    log-scalings a (n + 1), b (m + 1), every entry summed directly."""
+    lib = load()
+    C = _f64(C)
+    n, m = C.shape
+    a = _f64(a)
+    b = _f64(b)
+    assert a.shape == (n + 1,) and b.shape == (m + 1,)
+    return float(lib.potref_sk_error(n, m, _p(C), C.strides[0] // 8, float(gamma), _p(_f64(rt)), _p(_f64(ct_)),
+                                     float(s), float(A), _p(a), _p(b)))
+
+
+def plan_eval(Cp, gamma, f, g, alpha, beta, kappa, lam, pp, qq, Ce=None):
+    """A factored plan kappa diag(alpha) X~ diag(beta) + lam p' q'^T,
+    X~_ij = exp(f_i + g_j - Cp_ij / gamma), evaluated entry by entry.
+    Returns dict(rows, cols, cost (priced with Ce, default Cp), mass, min)."""
+    lib = load()
+    Cp = _f64(Cp)
+    Ce = Cp if Ce is None else _f64(Ce)
+    n, m = Cp.shape
+    assert Ce.shape == (n, m)
+    rows = np.empty(n)
+    cols = np.empty(m)
+    out = np.empty(3)
+    lib.potref_plan_eval(n, m, _p(Cp), Cp.strides[0] // 8, _p(Ce), Ce.strides[0] // 8, float(gamma),
+                         _p(_f64(f)), _p(_f64(g)), _p(_f64(alpha)), _p(_f64(beta)), float(kappa), float(lam),
+                         _p(_f64(pp)), _p(_f64(qq)), _p(rows), _p(cols), _p(out))
+    return dict(rows=rows, cols=cols, cost=float(out[0]), mass=float(out[1]), min=float(out[2]))
 
 
 def tuned_tol(r, c, gamma, p):

@@ -19,11 +19,27 @@ HIPCC_FLAGS = [
 ]
 
 
+OBJ_DIR = os.path.join(HERE, "_build")
+
+
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link libpot.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-Wl,-z,defs")]
+    procs, objs = [], []
+    for s in SOURCES:
+        obj = os.path.join(OBJ_DIR, s.replace(".hip", ".o"))
+        cmd = [hipcc] + compile_flags + ["-c", "-o", obj, os.path.join(CSRC, s)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((s, subprocess.Popen(cmd)))
+        objs.append(obj)
+    failed = [s for s, p in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + srcs
+    cmd = [hipcc, "--offload-arch=gfx950", "-fPIC", "-shared", "-Wl,-z,defs", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

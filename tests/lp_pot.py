@@ -11,26 +11,28 @@ Both are solved with scipy's HiGHS.
 import itertools
 
 import numpy as np
+import scipy.sparse as sp
 from scipy.optimize import linprog
 
 
 def pot_lp(C, r, c, s):
+    """Optimum of the slack LP and an optimal plan.  The constraint matrix is
+    sparse (three nonzeros per plan entry), so instances of a few hundred
+    points per side solve in seconds."""
     C = np.asarray(C, dtype=np.float64)
     n, m = C.shape
-    nv = n * m + n + m
-    A = np.zeros((n + m + 1, nv))
-    for i in range(n):
-        A[i, i * m:(i + 1) * m] = 1.0
-        A[i, n * m + i] = 1.0
-    for j in range(m):
-        A[n + j, j:n * m:m] = 1.0
-        A[n + j, n * m + n + j] = 1.0
-    A[n + m, :n * m] = 1.0
+    nm = n * m
+    ii = np.repeat(np.arange(n), m)
+    jj = np.tile(np.arange(m), n)
+    k = np.arange(nm)
+    rows = np.concatenate([ii, n + jj, np.full(nm, n + m), np.arange(n), n + np.arange(m)])
+    cols = np.concatenate([k, k, k, nm + np.arange(n), nm + n + np.arange(m)])
+    A = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n + m + 1, nm + n + m))
     b = np.concatenate([r, c, [s]])
     d = np.concatenate([C.ravel(), np.zeros(n + m)])
     res = linprog(d, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
     assert res.status == 0, res.message
-    return float(res.fun), res.x[:n * m].reshape(n, m)
+    return float(res.fun), res.x[:nm].reshape(n, m)
 
 
 def extended_ot_lp(C, r, c, s, A_corner=None):

@@ -50,6 +50,12 @@ MUTATIONS = {
                            "double gamma = 2.0 * eps / (49.0 * h);"),
     "tuned_log2_entropy": ("if (r[i] > 0.0) hr -= r[i] * log(r[i]);", "if (r[i] > 0.0) hr -= r[i] * log2(r[i]);"),
     "tuned_threshold_p": ("out3[1] = h * pow(gamma, p);", "out3[1] = h * gamma;"),
+    "sk_error_dummy_mass_swapped": ("double rh_d = sum_vec(m, ct) - s, ch_d = sum_vec(n, rt) - s;",
+                                    "double rh_d = sum_vec(n, rt) - s, ch_d = sum_vec(m, ct) - s;"),
+    "sk_error_corner_cost_zero": ("((i == n && j == m) ? A : 0.0);", "0.0;"),
+    "plan_eval_drops_rank_one": ("double v = kappa * (alpha[i] * xt * beta[j]) + lambda * pp[i] * qq[j];",
+                                 "double v = kappa * (alpha[i] * xt * beta[j]);"),
+    "plan_eval_prices_with_plan_cost": ("cx[j] = Ce[(long)i * lde + j] * v;", "cx[j] = Cp[(long)i * ldp + j] * v;"),
 }
 
 

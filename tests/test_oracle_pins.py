@@ -644,3 +644,75 @@ def test_aspot_variants_vs_exact_lp(oracle, variant, seed):
         bc = np.asarray(sol.trace.bchk[:it - 1])
         assert np.array_equal(bh, (2 * np.arange(it)) % 3)
         assert np.array_equal(bc, (2 * np.arange(it - 1) + 1) % 3)
+
+
+# ---------------------------------------------------------------------------
+# Checks of another solver's output point.  The Sinkhorn stopping error of
+# Algorithm 3 at extended scalings (a, b) relates to E(z) of Section 3.1 at
+# the ASPOT point of the same plan (appendix, "Reduction to Extended OT"):
+# with u_i = a_i + b_{m+1}, v_j = a_{n+1} + b_j, w = -(a_{n+1} + b_{m+1}),
+# the real rows and columns of the extended error are E's row and column
+# terms, and the dummy row (column) compares sum_j e^{v_j} (sum_i e^{u_i})
+# plus the corner entry with |c~|_1 - s (|r~|_1 - s); E's |T - s| term has
+# no counterpart.  potref_error and potref_sk_error are separate code.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(4))
+def test_sk_error_relates_to_aspot_error(oracle, seed):
+    C, r, c, s = _tiny(7, 9, 900 + seed, mass_r=1.1, mass_c=0.9, s_frac=0.7)
+    gamma, A = 0.07, 3.0
+    _, _, _, rt, ct_ = oracle.setup(r, c, s, 1e-2, cmax=float(C.max()), gamma=gamma)
+    g = np.random.default_rng(seed)
+    a = g.normal(-1.0, 0.6, 8)
+    b = g.normal(-1.5, 0.6, 10)
+    u, v, w = a[:-1] + b[-1], a[-1] + b[:-1], -(a[-1] + b[-1])
+    E = oracle.error(C, gamma, rt, ct_, s, u, v, w)
+    _, _, lT = oracle.stats(C, gamma, u, v, w)
+    corner = math.exp(a[-1] + b[-1] - A / gamma)
+    dummy = (abs(np.exp(v).sum() + corner - (ct_.sum() - s)) +
+             abs(np.exp(u).sum() + corner - (rt.sum() - s)))
+    expect = E - abs(math.exp(lT) - s) + dummy
+    assert abs(oracle.sk_error(C, gamma, rt, ct_, s, A, a, b) - expect) <= 1e-12 * max(1.0, expect)
+
+
+def test_sk_error_zero_columns_after_column_update(oracle):
+    """At the scalings Algorithm 3 returns, the columns were just fitted: the
+    error is the row part alone, and it is the error the loop reported."""
+    C, r, c, s = _tiny(8, 6, 950, mass_r=1.0, mass_c=1.2, s_frac=0.8)
+    gamma = 0.05
+    _, _, _, rt, ct_ = oracle.setup(r, c, s, 1e-2, cmax=float(C.max()), gamma=gamma)
+    a, b, it, err, st, _ = oracle.sinkhorn(C, gamma, 1e-6, rt, ct_, s, 8.0 / 1e-2, max_iter=10000)
+    assert st == 0
+    e = oracle.sk_error(C, gamma, rt, ct_, s, 8.0 / 1e-2, a, b)
+    assert abs(e - err) <= 1e-13
+    # column marginals exact: moving only the columns' target changes nothing
+    Ce = np.zeros((9, 7))
+    Ce[:8, :6] = C
+    Ce[8, 6] = 8.0 / 1e-2
+    X = np.exp(a[:, None] + b[None, :] - Ce / gamma)
+    chat = np.concatenate([ct_, [rt.sum() - s]])
+    assert np.max(np.abs(X.sum(0) - chat)) <= 1e-14
+
+
+# A factored plan evaluated entry by entry agrees with the dense rounding of
+# the same scalings (potref_round, which forms and rounds the dense matrix):
+# row and column sums, mass and cost; priced on another cost, the cost is
+# the dense plan's inner product with that cost.
+@pytest.mark.parametrize("seed", range(4))
+def test_plan_eval_matches_dense_rounding(oracle, seed):
+    C, r, c, s = _tiny(11, 8, 970 + seed, mass_r=1.0, mass_c=1.3, s_frac=0.6 + 0.1 * seed)
+    gamma = 0.04
+    g = np.random.default_rng(seed)
+    f = g.normal(-2.0, 0.5, 11)
+    gg = g.normal(-2.0, 0.5, 8)
+    rd = oracle.round_plan(C, gamma, f, gg, r, c, s, dense=True)
+    X = rd["X"]
+    Cb = I.bf16_bits_to_f64(I.to_bf16_bits(C.astype(np.float32)))
+    pe = oracle.plan_eval(C, gamma, f, gg, rd["alpha"], rd["beta"], rd["kappa"], rd["lam"], rd["pp"],
+                          rd["qq"], Ce=Cb)
+    assert np.max(np.abs(pe["rows"] - X.sum(1))) <= 1e-15
+    assert np.max(np.abs(pe["cols"] - X.sum(0))) <= 1e-15
+    assert abs(pe["mass"] - s) <= 1e-14
+    assert abs(pe["min"] - X.min()) <= 1e-16
+    assert abs(pe["cost"] - float(np.sum(Cb * X))) <= 1e-14
+    pe2 = oracle.plan_eval(C, gamma, f, gg, rd["alpha"], rd["beta"], rd["kappa"], rd["lam"], rd["pp"], rd["qq"])
+    assert abs(pe2["cost"] - rd["cost"]) <= 1e-14
