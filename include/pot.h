@@ -31,7 +31,8 @@
  *     workspace (size from pot_workspace_bytes*).
  *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).
  *     pot_solve synchronises the stream before returning, after which the
- *     host pot_result is filled and all device outputs are written.
+ *     host pot_result is filled and all device outputs are written; with
+ *     POT_FLAG_ASYNC it only enqueues (see that flag).
  *   - Dense costs are row-major with leading dimension ldc >= m (elements).
  *   - Arguments are checked before any work is enqueued that writes outside
  *     the workspace.  On POT_ERR_INVALID_ARG no output is written.
@@ -91,6 +92,18 @@ typedef struct {
 #define POT_FLAG_NO_ROUND 2u       /* skip the rounding passes (duals only) */
 #define POT_FLAG_NO_GRAPH 4u       /* launch every kernel from the host instead of replaying a
                                       captured HIP graph of check_every iterations */
+#define POT_FLAG_ASYNC 8u          /* pot_solve only enqueues its kernels on `stream` and returns:
+                                      no host synchronisation, no host read of device memory and
+                                      no memset node, so that the caller may capture the call in
+                                      a HIP graph.  `res` is then a DEVICE pointer to a pot_result
+                                      written when the stream reaches the end of the solve
+                                      (validation of r, c, s, eps and the cost happens on the
+                                      device and is reported there as POT_ERR_INVALID_ARG, with
+                                      no other output written); out->w must be NULL.  Every one
+                                      of max_iter iterations is enqueued (passes after the stop
+                                      return at once), so max_iter must be given, 1 .. 2^20.
+                                      Only host-side checks of sizes, pointers and options return
+                                      an error from the call itself */
 
 typedef struct {
     int32_t algo;          /* pot_algo */
@@ -124,6 +137,10 @@ typedef struct {
                               H(x) = -sum_i x_i ln x_i (0 ln 0 = 0), over the masses as given; a
                               positive gamma or tol above still overrides.  Needs H_min > 0 */
     double p;              /* exponent of the tuned rule, finite and >= 1 */
+    int32_t warm_check;    /* pot_solve with u0 / v0: 1 keeps the warm start only if
+                              phi(u0, v0, w0) < phi(0) (Section 2.1), else starts from zero
+                              (two more statistics passes); 0 always keeps it */
+    int32_t reserved0;     /* must be 0 */
 } pot_options;
 
 typedef struct {
@@ -139,6 +156,13 @@ typedef struct {
     double kappa, lambda, T2;   /* rounding factors (see the header comment) */
     double cost_scale, cmax;
     double w;              /* ASPOT: w at the output point (Sinkhorn: 0) */
+    double viol_row;       /* sum_i max(0, (Xbar 1)_i - r_i) over the FP64 row sums of the rounded plan
+                              (0 in exact arithmetic; what remains is FP64 rounding) */
+    double viol_col;       /* sum_j max(0, (Xbar^T 1)_j - c_j) */
+    double viol_mass;      /* |1^T Xbar 1 - s| */
+    double ext_a, ext_b;   /* Sinkhorn: log-scalings a_{n+1}, b_{m+1} of the dummy row and column
+                              of the extended instance at the output point (-inf for a zero
+                              dummy mass); ASPOT: 0 */
 } pot_result;
 
 typedef struct {

@@ -25,6 +25,9 @@ hipError_t launch_finish(const PassArgs& A, int algo, double* f, double* g, doub
                          hipStream_t st);
 hipError_t launch_copy_out(const PassArgs& A, double* alpha, double* beta, double* pp, double* qq,
                            hipStream_t st);
+hipError_t launch_zero_words(unsigned long long* p, int n, hipStream_t st);
+hipError_t launch_warm_decide(const PassArgs& A, int mode, hipStream_t st);
+hipError_t launch_result(const PassArgs& A, int algo, pot_result* res, hipStream_t st);
 
 hipError_t launch_stats_timed(const PassArgs& A, hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2,
                               hipEvent_t e3);
@@ -35,12 +38,16 @@ void warm_fill_desc(void* dst, const float* x, const float* y, const double* r, 
                     double* v0, double cost_scale, double inv_gamma, int n, int m);
 hipError_t launch_batched(const BArgs& B, int kind, int grid, hipStream_t st);
 
-static thread_local std::string g_last_error;
+// last error of this thread: a fixed buffer (recording an error allocates nothing)
+static thread_local char g_last_error[512];
 
-static pot_status fail(pot_status st, const std::string& msg) {
-    g_last_error = msg;
+static pot_status fail(pot_status st, const char* msg, const char* detail = nullptr) {
+    if (detail) std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", msg, detail);
+    else std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg);
     return st;
 }
+
+static void clear_error() { g_last_error[0] = '\0'; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -143,7 +150,7 @@ static pot_status check_problem(const pot_problem* p, const pot_options* o) {
     do {                                                                               \
         hipError_t e_ = (expr);                                                        \
         if (e_ != hipSuccess)                                                          \
-            return fail(POT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return fail(POT_ERR_DEVICE, #expr, hipGetErrorString(e_));                \
     } while (0)
 
 // pinned slots for convergence polling (host memory, allocated once per thread)
@@ -231,11 +238,29 @@ static hipError_t chunk_graph(const PassArgs& A, int algo, int chunk, hipGraphEx
     return hipSuccess;
 }
 
+// Largest max_iter of an asynchronous solve (every iteration is enqueued).
+constexpr int kAsyncMaxIter = 1 << 20;
+
+// One solve.  Synchronous (the default): the host polls a pinned done flag
+// between chunks of iterations and fills the host pot_result.  Asynchronous
+// (POT_FLAG_ASYNC, or `force_async` for the entry point without allocation):
+// everything is enqueued on `st`, every decision is taken on the device and
+// `res` is a device pointer.  `direct` launches every kernel from the host
+// (no graph is instantiated).
 static pot_status solve_one(const pot_problem* p, const pot_options* o, void* wsp, size_t ws_bytes,
-                            pot_result* res, const pot_outputs* out, hipStream_t st) {
+                            pot_result* res, const pot_outputs* out, hipStream_t st, bool force_async = false,
+                            bool direct = false) {
     pot_status cs = check_problem(p, o);
     if (cs != POT_OK) return cs;
     if (!res) return fail(POT_ERR_INVALID_ARG, "res is required");
+    if (o->warm_check < 0 || o->warm_check > 1) return fail(POT_ERR_INVALID_ARG, "warm_check is 0 or 1");
+    if (o->reserved0 != 0) return fail(POT_ERR_INVALID_ARG, "reserved0 must be 0");
+    const bool async = force_async || (o->flags & POT_FLAG_ASYNC);
+    if (async) {
+        if (o->max_iter < 1 || o->max_iter > kAsyncMaxIter)
+            return fail(POT_ERR_INVALID_ARG, "an asynchronous solve needs 1 <= max_iter <= 2^20 (every iteration is enqueued)");
+        if (out && out->w) return fail(POT_ERR_INVALID_ARG, "out->w (host) must be NULL in an asynchronous solve");
+    }
     const Geometry g = geometry(p, o);
     const size_t need = layout(p, g, nullptr, nullptr);
     if (!wsp || ws_bytes < need) return fail(POT_ERR_WORKSPACE, "workspace too small");
@@ -243,43 +268,49 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     char* base = (char*)wsp;
     Ws w;
     layout(p, g, base, &w);
-    pot_status ps = ensure_poll();
-    if (ps != POT_OK) return ps;
+    if (!async) {
+        pot_status ps = ensure_poll();
+        if (ps != POT_OK) return ps;
+    }
 
-    // --- cost scale and |C|_max (B10): one pass when not given
-    double cost_scale = 1.0, cmax = p->cmax;
-    if (p->kind == POT_COST_SQEUCLID_POINTS) {
-        cost_scale = p->cost_scale;
-        if (cost_scale <= 0.0 || cmax <= 0.0) {
-            unsigned long long* mb = maxbuf(base, need);
-            HIPCHK(hipMemsetAsync(mb, 0, 16, st));
+    // --- cost scale and |C|_max: one pass when not given.  Synchronously the
+    // host reads the maximum back and checks it; asynchronously the setup
+    // kernel reads it on the device.
+    double cost_scale = p->kind == POT_COST_SQEUCLID_POINTS ? p->cost_scale : 1.0, cmax = p->cmax;
+    const bool need_max = p->kind == POT_COST_SQEUCLID_POINTS ? (cost_scale <= 0.0 || cmax <= 0.0) : cmax <= 0.0;
+    const unsigned long long* maxdev = nullptr;
+    if (need_max) {
+        unsigned long long* mb = maxbuf(base, need);
+        HIPCHK(launch_zero_words(mb, 2, st));
+        if (p->kind == POT_COST_SQEUCLID_POINTS)
             HIPCHK(launch_cost_max(p->kind, nullptr, 0, p->x, p->y, p->n, p->m, p->d, mb, st));
+        else
+            HIPCHK(launch_cost_max(p->kind, p->C, p->ldc, nullptr, nullptr, p->n, p->m, 0, mb, st));
+        if (async) {
+            maxdev = mb;
+        } else {
             unsigned long long h[2];
             HIPCHK(hipMemcpyAsync(h, mb, 16, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             double mx;
             std::memcpy(&mx, &h[0], 8);
-            if (h[1] != 0) return fail(POT_ERR_INVALID_ARG, "non-finite point coordinates");
-            if (!(mx > 0.0)) return fail(POT_ERR_INVALID_ARG, "all points coincide (max cost 0)");
-            if (cost_scale <= 0.0) cost_scale = 1.0 / mx;
-            if (cmax <= 0.0) cmax = cost_scale * mx;
+            if (p->kind == POT_COST_SQEUCLID_POINTS) {
+                if (h[1] != 0) return fail(POT_ERR_INVALID_ARG, "non-finite point coordinates");
+                if (!(mx > 0.0)) return fail(POT_ERR_INVALID_ARG, "all points coincide (max cost 0)");
+                if (cost_scale <= 0.0) cost_scale = 1.0 / mx;
+                if (cmax <= 0.0) cmax = cost_scale * mx;
+            } else {
+                if (h[1] != 0) return fail(POT_ERR_INVALID_ARG, "cost has negative or non-finite entries");
+                cmax = mx;
+                if (!(cmax > 0.0)) return fail(POT_ERR_INVALID_ARG, "cost is identically 0 (|C|_max = 0)");
+            }
         }
-    } else if (cmax <= 0.0) {
-        unsigned long long* mb = maxbuf(base, need);
-        HIPCHK(hipMemsetAsync(mb, 0, 16, st));
-        HIPCHK(launch_cost_max(p->kind, p->C, p->ldc, nullptr, nullptr, p->n, p->m, 0, mb, st));
-        unsigned long long h[2];
-        HIPCHK(hipMemcpyAsync(h, mb, 16, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (h[1] != 0) return fail(POT_ERR_INVALID_ARG, "cost has negative or non-finite entries");
-        std::memcpy(&cmax, &h[0], 8);
-        if (!(cmax > 0.0)) return fail(POT_ERR_INVALID_ARG, "cost is identically 0 (|C|_max = 0)");
     }
 
     // every exponent log2(e) C_ij / gamma must stay below 2^29 (the kernels
     // split exponents into an int32 part and a fraction; the setup kernel
-    // checks the tuned rule's gamma)
-    if (o->gamma > 0.0 || o->gamma_rule == 0) {
+    // checks it again, also for the tuned rule's gamma and a device-side cmax)
+    if (!maxdev && (o->gamma > 0.0 || o->gamma_rule == 0)) {
         const int N = std::max(p->n, p->m);
         const double gam = o->gamma > 0.0 ? o->gamma : o->eps / (4.0 * std::log((double)N));
         if (!(1.4426950408889634 * cmax / gam < 536870912.0))
@@ -287,24 +318,31 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     }
 
     // --- setup (Algorithm 2, "Approximating POT") and validation of r, c, s
-    SetupArgs S;
+    SetupArgs S{};
     S.n = p->n; S.m = p->m; S.algo = o->algo; S.nx = g.nx; S.ny = g.ny;
     S.gamma_rule = o->gamma_rule; S.p = o->p;
     S.s = p->s; S.eps = o->eps; S.gamma_user = o->gamma; S.tol_user = o->tol; S.A_user = o->A;
     S.cmax = cmax; S.cost_scale = cost_scale; S.w0 = o->w0;
-    S.r = p->r; S.c = p->c; S.ws = w;
+    S.r = p->r; S.c = p->c; S.maxbuf = maxdev; S.kind = p->kind;
+    S.warm = (o->algo == POT_ASPOT && (o->u0 || o->v0)) ? 1 : 0;
+    S.ws = w;
     HIPCHK(launch_setup(S, st));
-    int32_t valid = 0;
-    HIPCHK(hipMemcpyAsync(&valid, &w.ctl->valid, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (valid != 0) {
-        static const char* why[] = {"", "r or c has a negative or non-finite entry",
-                                    "s must satisfy 0 < s <= min(|r|_1, |c|_1)", "gamma is not positive",
-                                    "eps~ capped to 0 (s equals a mass above 1) and no tol given",
-                                    "a smoothed marginal is not positive", "",
-                                    "|C|_max / gamma too large (exponents beyond 2^29)",
-                                    "the tuned rule needs min(H(r), H(c)) > 0"};
-        return fail(POT_ERR_INVALID_ARG, why[valid < 9 ? valid : 0]);
+    if (!async) {
+        int32_t valid = 0;
+        HIPCHK(hipMemcpyAsync(&valid, &w.ctl->valid, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (valid != 0) {
+            static const char* why[] = {"", "r or c has a negative or non-finite entry",
+                                        "s must satisfy 0 < s <= min(|r|_1, |c|_1)", "gamma is not positive",
+                                        "eps~ capped to 0 (s equals a mass above 1) and no tol given",
+                                        "a smoothed marginal is not positive", "",
+                                        "|C|_max / gamma too large (exponents beyond 2^29)",
+                                        "the tuned rule needs min(H(r), H(c)) > 0",
+                                        "cost has negative or non-finite entries",
+                                        "cost is identically 0 (|C|_max = 0)",
+                                        "non-finite point coordinates", "all points coincide (max cost 0)"};
+            return fail(POT_ERR_INVALID_ARG, why[valid < 13 ? valid : 0]);
+        }
     }
 
     PassArgs A;
@@ -318,23 +356,51 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     A.u0 = o->u0; A.v0 = o->v0; A.w0 = o->w0;
     A.force = o->force; A.force_len = o->force_len;
     A.trace_i = o->trace_i; A.trace_d = o->trace_d; A.trace_cap = o->trace_cap;
-    A.host_done = g_poll.flag;
+    A.host_done = async ? nullptr : g_poll.flag;
     A.ws = w;
 
-    // --- the iteration loop, enqueued in chunks; the decider sets a pinned
-    // host flag when the solve finishes, and the host reads it after the
-    // previous chunk has completed while the next one runs (no copy is
-    // enqueued between chunks)
-    const int chunk = o->check_every > 0 ? o->check_every : 16;
+    // --- start point.  With warm_check the zero start is evaluated first and
+    // the warm start is kept only if phi is lower there; the third start pass
+    // evaluates whichever was kept.  (The pinned flag is cleared before any
+    // pass that may set it.)
+    if (!async) *(volatile int32_t*)g_poll.flag = 0;
     if (o->algo == POT_ASPOT) {
+        if (S.warm && o->warm_check) {
+            PassArgs Z = A;
+            Z.u0 = nullptr;
+            Z.v0 = nullptr;
+            Z.w0 = 0.0;
+            Z.phase = PH_INIT;
+            HIPCHK(launch_stats(Z, st));
+            HIPCHK(launch_warm_decide(A, 0, st));
+            A.phase = PH_INIT;
+            HIPCHK(launch_stats(A, st));
+            HIPCHK(launch_warm_decide(A, 1, st));
+        }
         A.phase = PH_INIT;
         HIPCHK(launch_stats(A, st));
     }
+
+    // --- the iteration loop, enqueued in chunks (a captured graph of `chunk`
+    // iterations, unless disabled, the caller's stream is being captured or
+    // no graph may be instantiated).  Synchronously, the decider sets a pinned
+    // host flag when the solve finishes, and the host reads it after the
+    // previous chunk has completed while the next one runs (no copy is
+    // enqueued between chunks).  Asynchronously every iteration is enqueued;
+    // passes after the stop return at once.
+    const int chunk = o->check_every > 0 ? o->check_every : 16;
+    bool capturing = false;
+    if (st) {           // (the null stream cannot be captured)
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        HIPCHK(hipStreamIsCapturing(st, &cst));
+        capturing = cst != hipStreamCaptureStatusNone;
+    }
+    if (capturing && !async) return fail(POT_ERR_INVALID_ARG, "a solve inside a stream capture needs POT_FLAG_ASYNC");
+    hipGraphExec_t gexec = nullptr;
+    if (!direct && !capturing && !(o->flags & POT_FLAG_NO_GRAPH) && A.max_iter >= chunk)
+        HIPCHK(chunk_graph(A, o->algo, chunk, &gexec));
     int enq = 0, k = 0;
     bool done = false;
-    *(volatile int32_t*)g_poll.flag = 0;
-    hipGraphExec_t gexec = nullptr;
-    if (!(o->flags & POT_FLAG_NO_GRAPH) && A.max_iter >= chunk) HIPCHK(chunk_graph(A, o->algo, chunk, &gexec));
     while (!done && enq < A.max_iter) {
         const int todo = std::min(chunk, A.max_iter - enq);
         if (gexec && todo == chunk) {
@@ -345,11 +411,13 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
             HIPCHK(le);
         }
         enq += todo;
-        const int slot = k & 1;
-        HIPCHK(hipEventRecord(g_poll.ev[slot], st));
-        if (k > 0) {
-            HIPCHK(hipEventSynchronize(g_poll.ev[slot ^ 1]));
-            done = *(volatile int32_t*)g_poll.flag != 0;
+        if (!async) {
+            const int slot = k & 1;
+            HIPCHK(hipEventRecord(g_poll.ev[slot], st));
+            if (k > 0) {
+                HIPCHK(hipEventSynchronize(g_poll.ev[slot ^ 1]));
+                done = *(volatile int32_t*)g_poll.flag != 0;
+            }
         }
         ++k;
     }
@@ -359,14 +427,11 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
         HIPCHK(launch_stats(A, st));
     }
 
-    // --- form primal and round onto U(r, c, s) in FP64
+    // --- form primal and round onto U(r, c, s) in FP64 (the rounding kernels
+    // run only after a finished loop with representable statistics)
     HIPCHK(launch_finish(A, o->algo, out ? out->f : nullptr, out ? out->g : nullptr,
                          out ? out->u : nullptr, out ? out->v : nullptr, st));
-    Ctl hc;
-    HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const bool round = !(o->flags & POT_FLAG_NO_ROUND) && hc.status != POT_ERR_NUMERIC && hc.done;
-    if (round) {
+    auto enqueue_round = [&]() -> pot_status {
         for (int ph : {PH_R1, PH_R2, PH_R3}) {
             A.phase = ph;
             HIPCHK(launch_round(A, st));
@@ -377,32 +442,35 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
             HIPCHK(launch_round(A, st));
         }
         if (out) HIPCHK(launch_copy_out(A, out->alpha, out->beta, out->pp, out->qq, st));
-        HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        return POT_OK;
+    };
+    if (async) {
+        if (!(o->flags & POT_FLAG_NO_ROUND)) {
+            pot_status rs = enqueue_round();
+            if (rs != POT_OK) return rs;
+        }
+        HIPCHK(launch_result(A, o->algo, res, st));
+        clear_error();
+        return POT_OK;
     }
+    Ctl hc;
+    HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (!(o->flags & POT_FLAG_NO_ROUND) && hc.status != POT_ERR_NUMERIC && hc.done) {
+        pot_status rs = enqueue_round();
+        if (rs != POT_OK) return rs;
+    }
+    HIPCHK(launch_result(A, o->algo, nullptr, st));
+    HIPCHK(hipMemcpyAsync(&hc, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     if (!hc.done) return fail(POT_ERR_DEVICE, "solver loop ended without a decision");
 
     std::memset(res, 0, sizeof(*res));
-    res->status = hc.status;
-    res->iters = hc.iters;
-    res->algo = o->algo;
-    res->used_warm = (o->u0 || o->v0) ? 1 : 0;
-    res->cost = hc.cost;
-    res->E = hc.E;
-    res->gamma = hc.gamma;
-    res->tol = hc.tol;
-    res->phi = hc.phichk;
-    res->mass = hc.mass;
-    res->kappa = hc.kappa;
-    res->lambda = hc.lambda;
-    res->T2 = hc.T2;
-    res->cost_scale = cost_scale;
-    res->cmax = cmax;
-    res->w = o->algo == POT_ASPOT ? hc.wz : 0.0;
+    fill_result(hc, o->algo, *res);
     if (out && out->w) *out->w = res->w;
-    if (hc.status == POT_ERR_NUMERIC) g_last_error = "non-finite row or column sum (overflow)";
-    else if (hc.status == POT_ERR_NO_CONVERGENCE) g_last_error = "max_iter reached before E <= tol";
-    else g_last_error.clear();
+    if (hc.status == POT_ERR_NUMERIC) fail(POT_ERR_NUMERIC, "non-finite row or column sum (overflow)");
+    else if (hc.status == POT_ERR_NO_CONVERGENCE) fail(POT_ERR_NO_CONVERGENCE, "max_iter reached before E <= tol");
+    else clear_error();
     return (pot_status)hc.status;
 }
 
@@ -731,7 +799,7 @@ pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void*
             return fail(POT_ERR_INVALID_ARG, "pot_time_pass needs cmax (and cost_scale) given");
         Ws w;
         layout(prob, g, (char*)ws, &w);
-        SetupArgs S;
+        SetupArgs S{};
         S.n = prob->n; S.m = prob->m; S.algo = POT_ASPOT; S.nx = g.nx; S.ny = g.ny;
         S.gamma_rule = opts->gamma_rule; S.p = opts->p;
         S.s = prob->s; S.eps = opts->eps; S.gamma_user = opts->gamma; S.tol_user = opts->tol;
@@ -825,7 +893,7 @@ const char* pot_status_string(pot_status st) {
     }
 }
 
-const char* pot_last_error(void) { return g_last_error.c_str(); }
+const char* pot_last_error(void) { return g_last_error; }
 
 const char* pot_version(void) { return "libpot 0.1 (gfx950)"; }
 

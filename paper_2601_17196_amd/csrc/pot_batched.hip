@@ -583,6 +583,7 @@ __device__ bool member_round(Member& M, BShared& S) {
         double q2 = cm[j] - be * cs;
         q2 = q2 > 0.0 ? q2 : 0.0;
         w.qq[j] = q2;
+        w.dv[j] = be * cs;                 // (X''^T 1)_j, for the marginal check
         v2[0] += be * cs;
         v2[1] += q2;
         v2[2] += isfinite(cs) ? 0.0 : 1.0;
@@ -607,6 +608,7 @@ __device__ bool member_round(Member& M, BShared& S) {
             double p = r[i] - rs;
             p = p > 0.0 ? p : 0.0;
             w.pp[i] = p;
+            w.du[i] = rs;                  // (X'' 1)_i
             S.R[rr] = rc;
             S.a[rr] = p;
             S.b[rr] = p * rq;
@@ -652,6 +654,36 @@ __device__ bool member_round(Member& M, BShared& S) {
         c.mass = c.kappa * T2 + c.lambda * c.np * c.nq;
     }
     __syncthreads();
+    // marginal violations of Xbar = kappa X'' + lambda p' q'^T from its FP64
+    // sums: (Xbar 1)_i = kappa (X'' 1)_i + lambda |q'|_1 p'_i, and the columns
+    // likewise (every member holds every column; the rows are summed over
+    // the group)
+    {
+        const double lr = c.lambda > 0.0 ? c.lambda * c.nq : 0.0;
+        const double lc = c.lambda > 0.0 ? c.lambda * c.np : 0.0;
+        double vv[2] = {0.0, 0.0};
+        for (int rr = tid; rr < nr; rr += kBThreads) {
+            const int i = r0 + rr;
+            vv[0] += fmax(c.kappa * w.du[i] + lr * w.pp[i] - r[i], 0.0);
+        }
+        for (int j = tid; j < m; j += kBThreads) vv[1] += fmax(c.kappa * w.dv[j] + lc * w.qq[j] - cm[j], 0.0);
+        block_sum<2, kBWaves>(vv, S.red);
+        if (M.G > 1) {
+            if (tid == 0) st_agent(&M.rowsc[(int64_t)M.mem * kScal + 4], vv[0]);
+            if (!group_sync(M, S)) return false;
+            if (tid == 0) {
+                vv[0] = 0.0;
+                for (int g = 0; g < M.G; ++g) vv[0] += ld_agent(&M.rowsc[(int64_t)g * kScal + 4]);
+            }
+        }
+        if (tid == 0) {
+            c.viol_row = vv[0];
+            c.viol_col = vv[1];
+            c.viol_mass = fabs(c.mass - c.s);
+            c.rounded = 1;
+        }
+        __syncthreads();
+    }
     return true;
 }
 
@@ -837,23 +869,12 @@ __device__ void member_solve(const BArgs& B, BShared& S, int inst, int mem) {
     }
     if (mem == 0 && tid == 0) {
         const Ctl& c = S.ctl;
-        pot_result& R = B.res[inst];
+        pot_result R;
+        fill_result(c, B.algo, R);
         R.status = !ok ? POT_ERR_DEVICE : (valid ? POT_ERR_INVALID_ARG : c.status);
-        R.iters = c.iters;
-        R.algo = B.algo;
         R.used_warm = S.used_warm;
-        R.cost = c.cost;
-        R.E = c.E;
-        R.gamma = c.gamma;
-        R.tol = c.tol;
-        R.phi = c.phichk;
-        R.mass = c.mass;
-        R.kappa = c.kappa;
-        R.lambda = c.lambda;
-        R.T2 = c.T2;
         R.cost_scale = 1.0;
-        R.cmax = c.cmax;
-        R.w = B.algo == POT_ASPOT ? c.wz : 0.0;
+        B.res[inst] = R;
     }
     __syncthreads();
 }

@@ -294,9 +294,11 @@ __device__ __forceinline__ double eval_point(const PassArgs& A, const Ctl& c, co
                                            int side, int i, bool writer) {
     const int par = c.t & 1;
     switch (PH) {
-    case PH_INIT:
-        if (writer) { V.chk0[i] = q.q0; V.til0[i] = q.q0; }
-        return q.q0;
+    case PH_INIT: {
+        const double x0 = c.cold ? 0.0 : q.q0;       // (the warm-start check may fall back to zero)
+        if (writer) { V.chk0[i] = x0; V.til0[i] = x0; }
+        return x0;
+    }
     case PH_BAR: {
         // z-check^t = GreenkhornStep(z^{t-1}): d holds this block's delta at z^{t-1}
         double xc = q.q0;
@@ -336,7 +338,7 @@ template <int PH>
 __device__ __forceinline__ double w_point(const PassArgs& A, const Ctl& c) {
     const int par = c.t & 1;
     switch (PH) {
-    case PH_INIT: return A.w0;
+    case PH_INIT: return c.cold ? 0.0 : A.w0;
     case PH_BAR: return (1.0 - c.theta) * pick2(c.wchk, par) + c.theta * pick2(c.wtil, par);
     case PH_GRAVE: return c.wgrave;
     case PH_Z: return c.wz;
@@ -472,10 +474,11 @@ __device__ __forceinline__ void decide_logic(const PassArgs& A, Ctl& c, const do
     }
     switch (A.phase) {
     case PH_INIT: {
+        const double w0 = c.cold ? 0.0 : A.w0;
         c.T = Tv;
-        c.phichk = Tv + Rs[1] + Cs[1] - Rs[2] - Cs[2] - A.w0 * c.s;
-        c.wchk[0] = A.w0;
-        c.wtil[0] = A.w0;
+        c.phichk = Tv + Rs[1] + Cs[1] - Rs[2] - Cs[2] - w0 * c.s;
+        c.wchk[0] = w0;
+        c.wtil[0] = w0;
         c.theta = 1.0;
         c.t = 0;
         break;
@@ -670,6 +673,12 @@ __device__ inline void setup_fill(Ctl& c, const SetupIn& S, double gamma, double
     c.out_par = 0;
     c.cyc = 0;
     c.valid = valid;
+    c.viol_row = c.viol_col = c.viol_mass = 0.0;
+    c.phi0 = 0.0;
+    c.cold = 0;
+    c.used_warm = 0;
+    c.rounded = 0;
+    c.pad0 = 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -47,13 +47,44 @@ struct Ctl {
     double ad[2], bd, lse_a, lse_b;
     // rounding
     double T2, nq, np, cost1, pcq, kappa, lambda, cost, mass;
+    double viol_row, viol_col, viol_mass;   // excess of the rounded plan's sums over r, c and |mass - s|
+    double phi0;           // warm-start check: phi at the zero start
     int32_t t, done, status, bhat, pick, bchk, iters, nonfinite;
     int32_t out_par;       // Sinkhorn: parity slot of the output a
     int32_t cyc;           // cyclic block counter
     int32_t valid;         // setup status (0 ok)
     int32_t wide;          // a tile of the pass just made had its shift beyond the normal
                            // FP64 window (set by the tile pass, cleared by the decider)
+    int32_t cold;          // the start pass evaluates the zero start instead of (u0, v0, w0)
+    int32_t used_warm;     // the solve runs from the caller's warm start
+    int32_t rounded;       // the rounding passes ran (factors, cost and mass are set)
+    int32_t pad0;
 };
+
+// The result block of a solve from its control block (host and device).
+__host__ __device__ inline void fill_result(const Ctl& c, int algo, pot_result& R) {
+    R.status = c.done ? c.status : POT_ERR_DEVICE;
+    R.iters = c.iters;
+    R.algo = algo;
+    R.used_warm = c.used_warm;
+    R.cost = c.cost;
+    R.E = c.E;
+    R.gamma = c.gamma;
+    R.tol = c.tol;
+    R.phi = c.phichk;
+    R.mass = c.mass;
+    R.kappa = c.kappa;
+    R.lambda = c.lambda;
+    R.T2 = c.T2;
+    R.cost_scale = c.cost_scale;
+    R.cmax = c.cmax;
+    R.w = algo == POT_ASPOT ? c.wz : 0.0;
+    R.viol_row = c.viol_row;
+    R.viol_col = c.viol_col;
+    R.viol_mass = c.viol_mass;
+    R.ext_a = algo == POT_SINKHORN ? (c.out_par ? c.ad[1] : c.ad[0]) : 0.0;
+    R.ext_b = algo == POT_SINKHORN ? c.bd : 0.0;
+}
 
 // Pointers into one solve's workspace.
 struct Ws {
@@ -106,6 +137,11 @@ struct SetupArgs {
     double s, eps, gamma_user, tol_user, A_user, cmax, cost_scale, w0;
     const double* r;
     const double* c;
+    // device-computed cost maximum {FP64 bits of max C (or max |x - y|^2), count of bad
+    // entries}, or NULL when cmax and cost_scale are given
+    const unsigned long long* maxbuf;
+    int32_t kind;          // pot_cost_kind (how maxbuf is read)
+    int32_t warm;          // u0 or v0 given
     Ws ws;
 };
 

@@ -717,6 +717,10 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
     __shared__ double s_cols[4][kMaxBC];
     __shared__ int s_flags[4];
     Ctl& c = *A.ws.ctl;
+    // no rounding without a finished loop and representable statistics (a
+    // uniform test: every workgroup reads the same words)
+    if (c.valid != 0 || !c.done || c.status == POT_ERR_NUMERIC) return;
+    if (A.phase == PH_R4 && !c.rounded) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = tile_index();
     const int tx = tile % A.nx, ty = tile / A.nx;
@@ -807,6 +811,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
                 double p = A.r[i] - rs;
                 p = p > 0.0 ? p : 0.0;
                 w.pp[i] = p;
+                w.du[i] = rs;          // (X'' 1)_i, for the marginal check of the result
                 acc[0] += rc;          // <C, X''>
                 acc[1] += p;           // |p'|_1
                 acc[2] += p * rq;      // p'^T C q'
@@ -832,6 +837,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
             double q2 = A.c[j] - be * cs;
             q2 = q2 > 0.0 ? q2 : 0.0;
             w.qq[j] = q2;
+            w.dv[j] = be * cs;        // (X''^T 1)_j
             acc[0] += be * cs;        // T''
             acc[1] += q2;             // |q'|_1
             acc[7] += isfinite(cs) ? 0.0 : 1.0;
@@ -870,6 +876,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
                     } else { c.kappa = 1.0; c.lambda = 0.0; }
                     c.cost = c.kappa * c.cost1 + c.lambda * c.pcq;
                     c.mass = c.kappa * T2 + c.lambda * c.np * c.nq;
+                    c.rounded = 1;
                 }
                 st_agent(&w.glob[0], 0);
             }
@@ -885,8 +892,28 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
     __shared__ double s_v[5];
     Ctl& c = *S.ws.ctl;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const SetupIn in = {S.n, S.m, S.algo, S.gamma_rule, S.p, S.s, S.eps, S.gamma_user, S.tol_user, S.A_user,
-                        S.cmax, S.cost_scale, S.w0};
+    SetupIn in = {S.n, S.m, S.algo, S.gamma_rule, S.p, S.s, S.eps, S.gamma_user, S.tol_user, S.A_user,
+                  S.cmax, S.cost_scale, S.w0};
+    // the cost maximum computed on the device (a solve that does not read it
+    // back): |C|_max, or for points the scale 1 / max |x - y|^2 and cmax
+    int vmax = 0;
+    if (S.maxbuf) {
+        const double mx = __longlong_as_double((long long)S.maxbuf[0]);
+        const bool bad = S.maxbuf[1] != 0;
+        if (S.kind == POT_COST_SQEUCLID_POINTS) {
+            if (bad) vmax = 11;
+            else if (!(mx > 0.0)) vmax = 12;
+            else {
+                if (!(in.cost_scale > 0.0)) in.cost_scale = 1.0 / mx;
+                if (!(in.cmax > 0.0)) in.cmax = in.cost_scale * mx;
+            }
+        } else {
+            if (bad) vmax = 9;
+            else if (!(mx > 0.0)) vmax = 10;
+            else in.cmax = mx;
+        }
+        if (vmax) { in.cmax = 1.0; in.cost_scale = 1.0; }
+    }
     // block reduction of K sums over the 1024 threads (16 waves)
     auto reduce = [&](auto& v) {
         constexpr int K = sizeof(v) / sizeof(double);
@@ -925,8 +952,9 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
     const double sr = v[0], sc = v[1];
     double gamma, et, tol;
     int valid = setup_params(in, sr, sc, v[2], v[3], v[4], gamma, et, tol);
+    if (vmax) valid = vmax;
     // every exponent log2(e) C_ij / gamma must stay below 2^29 (exponent split)
-    if (valid == 0 && !(kLog2e * S.cmax / gamma < 536870912.0)) valid = 7;
+    if (valid == 0 && !(kLog2e * in.cmax / gamma < 536870912.0)) valid = 7;
     // smoothed marginals r~, c~ (and their logs)
     double u[3] = {0.0, 0.0, 0.0};      // |r~|_1, |c~|_1, non-positive entries
     for (int i = tid; i < S.n; i += nt) {
@@ -954,7 +982,10 @@ __global__ __launch_bounds__(1024) void setup_kernel(SetupArgs S) {
     for (int k = tid; k < S.nx * S.ny; k += nt) S.ws.tshift[k] = 0;
     for (int k = tid; k < S.nx; k += nt) S.ws.colcnt[k] = 0;
     if (tid < 4) S.ws.glob[tid] = 0;
-    if (tid == 0) setup_fill(c, in, gamma, tol, sr, sc, u[0], u[1], valid);
+    if (tid == 0) {
+        setup_fill(c, in, gamma, tol, sr, sc, u[0], u[1], valid);
+        c.used_warm = S.warm;
+    }
 }
 
 // max_ij C_ij and a check that C is finite and >= 0 (dense kinds), or
@@ -996,6 +1027,7 @@ __global__ __launch_bounds__(kThreads) void cost_max_kernel(const void* C, int64
 // rounding slots (ubar, vbar) and the optional caller vectors.
 __global__ void finish_duals(PassArgs A, int algo, double* fo, double* go, double* uo, double* vo) {
     Ctl& c = *A.ws.ctl;
+    if (c.valid != 0) return;               // invalid problem: no output is written
     const Ws& w = A.ws;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < A.n) {
@@ -1019,6 +1051,7 @@ __global__ void finish_duals(PassArgs A, int algo, double* fo, double* go, doubl
 __global__ void copy_out(PassArgs A, double* alpha, double* beta, double* pp, double* qq) {
     const Ws& w = A.ws;
     const Ctl& c = *A.ws.ctl;
+    if (!c.rounded) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < A.n) {
         if (alpha) alpha[k] = w.alpha[k];
@@ -1027,6 +1060,72 @@ __global__ void copy_out(PassArgs A, double* alpha, double* beta, double* pp, do
     if (k < A.m) {
         if (beta) beta[k] = w.beta[k];
         if (qq) qq[k] = c.lambda > 0.0 ? w.qq[k] : 0.0;
+    }
+}
+
+// Clear `n` 64-bit words (a kernel, not a memset node, so that a captured
+// solve replays correctly).
+__global__ void zero_words(unsigned long long* p, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0ull;
+}
+
+// Warm-start check of pot_solve.  mode 0, after the start pass at zero: keep
+// phi(0).  mode 1, after the start pass at (u0, v0, w0): keep the warm start
+// only if its phi is below phi(0) (a start whose statistics are not
+// representable counts as worse); otherwise the next start pass evaluates
+// the zero start.
+__global__ void warm_decide(PassArgs A, int mode) {
+    Ctl& c = *A.ws.ctl;
+    if (threadIdx.x != 0 || c.valid != 0) return;
+    if (mode == 0) {
+        c.phi0 = c.done ? NAN : c.phichk;
+        return;
+    }
+    if (c.phi0 != c.phi0) return;          // the zero start itself ended the solve
+    if (c.done) {                          // the warm start's statistics overflowed
+        if (A.host_done) __hip_atomic_store(A.host_done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        c.done = 0;
+        c.status = POT_OK;
+        c.nonfinite = 0;
+        c.iters = 0;
+        c.cold = 1;
+        c.used_warm = 0;
+    } else if (!(c.phichk < c.phi0)) {
+        c.cold = 1;
+        c.used_warm = 0;
+    }
+}
+
+// Marginal violations of the rounded plan Xbar = kappa X'' + lambda p' q'^T
+// from its FP64 sums, (Xbar 1)_i = kappa (X'' 1)_i + lambda |q'|_1 p'_i and
+// the same for the columns, and |1^T Xbar 1 - s|; with res != NULL the
+// result block of the solve is written to device memory.
+__global__ __launch_bounds__(1024) void result_kernel(PassArgs A, int algo, pot_result* res) {
+    __shared__ double s_red[16 * 2];
+    Ctl& c = *A.ws.ctl;
+    const Ws& w = A.ws;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double v0 = 0.0, v1 = 0.0;
+    if (c.rounded) {
+        const double lr = c.lambda > 0.0 ? c.lambda * c.nq : 0.0;
+        const double lc = c.lambda > 0.0 ? c.lambda * c.np : 0.0;
+        for (int i = tid; i < A.n; i += blockDim.x) v0 += fmax(c.kappa * w.du[i] + lr * w.pp[i] - A.r[i], 0.0);
+        for (int j = tid; j < A.m; j += blockDim.x) v1 += fmax(c.kappa * w.dv[j] + lc * w.qq[j] - A.c[j], 0.0);
+    }
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    if (lane == 0) { s_red[wave] = v0; s_red[16 + wave] = v1; }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += s_red[k]; b += s_red[16 + k]; }
+        if (c.rounded) {
+            c.viol_row = a;
+            c.viol_col = b;
+            c.viol_mass = fabs(c.mass - c.s);
+        }
+        if (res) fill_result(c, algo, *res);
     }
 }
 
@@ -1118,6 +1217,21 @@ hipError_t launch_cost_max(int kind, const void* C, int64_t ldc, const float* x,
 hipError_t launch_finish(const PassArgs& A, int algo, double* f, double* g, double* u, double* v, hipStream_t st) {
     int len = A.n > A.m ? A.n : A.m;
     finish_duals<<<(len + 255) / 256, 256, 0, st>>>(A, algo, f, g, u, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(unsigned long long* p, int n, hipStream_t st) {
+    zero_words<<<(n + 63) / 64, 64, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_decide(const PassArgs& A, int mode, hipStream_t st) {
+    warm_decide<<<1, 64, 0, st>>>(A, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_result(const PassArgs& A, int algo, pot_result* res, hipStream_t st) {
+    result_kernel<<<1, 1024, 0, st>>>(A, algo, res);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ __all__ = [
     "load", "lib_path", "ASPOT", "SINKHORN", "COST_F32", "COST_BF16", "COST_POINTS",
     "FLAG_WANT_PLAN", "FLAG_NO_ROUND", "Problem", "Options", "Result", "Outputs",
     "solve", "solve_batched", "workspace_bytes", "status_string", "last_error", "SolveOutput",
-    "PotError", "time_pass",
+    "PotError", "time_pass", "result_from_device", "FLAG_ASYNC",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +25,7 @@ _LIB = os.path.join(HERE, "libpot.so")
 
 ASPOT, SINKHORN = 0, 1
 COST_F32, COST_BF16, COST_POINTS = 0, 1, 3
-FLAG_WANT_PLAN, FLAG_NO_ROUND, FLAG_NO_GRAPH = 1, 2, 4
+FLAG_WANT_PLAN, FLAG_NO_ROUND, FLAG_NO_GRAPH, FLAG_ASYNC = 1, 2, 4, 8
 
 OK, ERR_INVALID_ARG, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_WORKSPACE, ERR_UNSUPPORTED = range(7)
 
@@ -50,7 +50,8 @@ class Options(ct.Structure):
                 ("flags", ct.c_uint32), ("u0", ct.c_void_p), ("v0", ct.c_void_p), ("w0", ct.c_double),
                 ("force", ct.c_void_p), ("force_len", ct.c_int32), ("trace_i", ct.c_void_p),
                 ("trace_d", ct.c_void_p), ("trace_cap", ct.c_int32), ("tile_rows", ct.c_int32),
-                ("member_elems", ct.c_int32), ("gamma_rule", ct.c_int32), ("p", ct.c_double)]
+                ("member_elems", ct.c_int32), ("gamma_rule", ct.c_int32), ("p", ct.c_double),
+                ("warm_check", ct.c_int32), ("reserved0", ct.c_int32)]
 
 
 class BatchOutputs(ct.Structure):
@@ -72,7 +73,9 @@ class Result(ct.Structure):
                 ("used_warm", ct.c_int32), ("cost", ct.c_double), ("E", ct.c_double),
                 ("gamma", ct.c_double), ("tol", ct.c_double), ("phi", ct.c_double),
                 ("mass", ct.c_double), ("kappa", ct.c_double), ("lambda_", ct.c_double),
-                ("T2", ct.c_double), ("cost_scale", ct.c_double), ("cmax", ct.c_double), ("w", ct.c_double)]
+                ("T2", ct.c_double), ("cost_scale", ct.c_double), ("cmax", ct.c_double), ("w", ct.c_double),
+                ("viol_row", ct.c_double), ("viol_col", ct.c_double), ("viol_mass", ct.c_double),
+                ("ext_a", ct.c_double), ("ext_b", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -176,7 +179,8 @@ def make_problem(r, c, s, C=None, x=None, y=None, kind=None, ldc=None, cost_scal
 
 def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, block_rule=0,
                  step_rule=0, check_every=0, flags=0, u0=None, v0=None, w0=0.0, force=None,
-                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0, member_elems=0, gamma_rule=0, p=1.0):
+                 trace_i=None, trace_d=None, trace_cap=0, tile_rows=0, member_elems=0, gamma_rule=0, p=1.0,
+                 warm_check=0):
     o = Options()
     o.algo = int(algo)
     o.max_iter = int(max_iter)
@@ -198,6 +202,8 @@ def make_options(eps, algo=ASPOT, max_iter=100000, gamma=0.0, tol=0.0, A=0.0, bl
     o.member_elems = int(member_elems)
     o.gamma_rule = int(gamma_rule)
     o.p = float(p)
+    o.warm_check = int(warm_check)
+    o.reserved0 = 0
     return o
 
 
@@ -221,12 +227,25 @@ class SolveOutput:
     plan: object = None
     trace_i: object = None
     trace_d: object = None
+    result_dev: object = None     # asynchronous solve: device bytes of the pot_result
+    workspace: object = None      # the workspace tensor (kept alive with the output)
+
+
+def result_from_device(t) -> dict:
+    """The pot_result an asynchronous solve wrote to device memory (a uint8
+    tensor of sizeof(pot_result) bytes), as a dict."""
+    raw = bytes(t.cpu().numpy().tobytes())
+    return Result.from_buffer_copy(raw).as_dict()
 
 
 def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=0.0, cmax=0.0,
           algo=ASPOT, want_plan=False, want_factors=True, workspace=None, stream=None,
-          raise_on_error=True, trace_cap=0, **opt_kw):
-    """Solve one POT instance through pot_solve.  Tensors must be on the GPU."""
+          raise_on_error=True, trace_cap=0, async_=False, **opt_kw):
+    """Solve one POT instance through pot_solve.  Tensors must be on the GPU.
+
+    async_=True sets POT_FLAG_ASYNC: the call only enqueues, the result block
+    is written to a device tensor (SolveOutput.result_dev, read it with
+    result_from_device after the stream has reached it) and result is {}."""
     import torch
     lib = load()
     dev = r.device
@@ -235,7 +254,7 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     if trace_cap > 0:
         tr_i = torch.full((trace_cap * 3,), -9, dtype=torch.int32, device=dev)
         tr_d = torch.full((trace_cap * 4,), float("nan"), dtype=torch.float64, device=dev)
-    flags = (FLAG_WANT_PLAN if want_plan else 0) | int(opt_kw.pop("flags", 0))
+    flags = (FLAG_WANT_PLAN if want_plan else 0) | (FLAG_ASYNC if async_ else 0) | int(opt_kw.pop("flags", 0))
     opts = make_options(eps, algo=algo, flags=flags, trace_i=tr_i, trace_d=tr_d, trace_cap=trace_cap,
                         **opt_kw)
     nbytes = workspace_bytes(prob, opts)
@@ -261,6 +280,17 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     out.plan = _ptr(so.plan)
     out.f, out.g, out.u, out.v = _ptr(so.f), _ptr(so.g), _ptr(so.u), _ptr(so.v)
     out.alpha, out.beta, out.pp, out.qq = _ptr(so.alpha), _ptr(so.beta), _ptr(so.pp), _ptr(so.qq)
+    so.trace_i, so.trace_d = tr_i, tr_d
+    so.workspace = workspace
+    if flags & FLAG_ASYNC:
+        so.result_dev = torch.zeros(ct.sizeof(Result), dtype=torch.uint8, device=dev)
+        st = lib.pot_solve(ct.byref(prob), ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(avail),
+                           ct.cast(ct.c_void_p(so.result_dev.data_ptr()), ct.POINTER(Result)), ct.byref(out),
+                           _stream_ptr(stream))
+        so.status = int(st)
+        if raise_on_error and st != OK:
+            raise PotError(st, last_error())
+        return so
     out.w = ct.pointer(wbox)
     res = Result()
     st = lib.pot_solve(ct.byref(prob), ct.byref(opts), ct.c_void_p(aligned), ct.c_size_t(avail),
@@ -268,7 +298,6 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     so.status = int(st)
     so.result = res.as_dict()
     so.w = wbox.value
-    so.trace_i, so.trace_d = tr_i, tr_d
     if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
         raise PotError(st, last_error())
     return so

@@ -18,3 +18,17 @@ def oracle():
     from oracle import potref
     potref.load()
     return potref
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """How the free-running GPU parity cases were judged (shown even with -q)."""
+    try:
+        from tests.gpu_common import PARITY_TALLY
+    except Exception:
+        return
+    strict, d1 = PARITY_TALLY["strict"], PARITY_TALLY["def1"]
+    if not strict and not d1:
+        return
+    terminalreporter.write_line(
+        f"parity: {len(strict)} free-running cases matched the oracle's decisions (1e-6 element by element), "
+        f"{len(d1)} took a near tie the other way and passed the Definition 1 check: {', '.join(d1) or '-'}")

@@ -15,10 +15,11 @@ import scipy.sparse as sp
 from scipy.optimize import linprog
 
 
-def pot_lp(C, r, c, s):
-    """Optimum of the slack LP and an optimal plan.  The constraint matrix is
-    sparse (three nonzeros per plan entry), so instances of a few hundred
-    points per side solve in seconds."""
+def pot_lp(C, r, c, s, duals=False):
+    """Optimum of the slack LP and an optimal plan (and, with duals=True, the
+    optimal dual (alpha, beta, lam) of its equality constraints).  The
+    constraint matrix is sparse (three nonzeros per plan entry), so instances
+    of a few hundred points per side solve in seconds."""
     C = np.asarray(C, dtype=np.float64)
     n, m = C.shape
     nm = n * m
@@ -32,7 +33,39 @@ def pot_lp(C, r, c, s):
     d = np.concatenate([C.ravel(), np.zeros(n + m)])
     res = linprog(d, A_eq=A, b_eq=b, bounds=(0, None), method="highs")
     assert res.status == 0, res.message
+    if duals:
+        y = res.eqlin.marginals
+        return float(res.fun), res.x[:nm].reshape(n, m), (y[:n], y[n:n + m], float(y[n + m]))
     return float(res.fun), res.x[:nm].reshape(n, m)
+
+
+def dual_lower_bound(C, r, c, s, beta, lam, chunk=1024):
+    """A lower bound on the POT optimum from any column duals beta (m) and
+    mass dual lam, by weak duality for the slack LP.  Its dual is
+        max r.alpha + c.beta + s lam
+        s.t. alpha_i + beta_j + lam <= C_ij, alpha <= 0, beta <= 0
+    (one constraint per plan entry and per slack).  With beta' = min(beta, 0)
+    and alpha_i = min(0, min_j (C_ij - beta'_j - lam)) the point is feasible;
+    then beta''_j = min(0, min_i (C_ij - alpha_i - lam)) keeps it feasible
+    and can only raise the value, which is <= OPT.  C: an n x m array, or a
+    function rows(i0, i1) returning rows i0..i1-1 in FP64 (for sizes whose
+    dense FP64 cost is better not kept).  Entropic duals map to LP duals by
+    beta = gamma v, lam = gamma w (X_ij = exp(u_i + v_j + w - C_ij / gamma),
+    slack p_i = e^{u_i})."""
+    r = np.asarray(r, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    n, m = len(r), len(c)
+    rows = C if callable(C) else (lambda i0, i1: np.asarray(C[i0:i1], dtype=np.float64))
+    b1 = np.minimum(np.asarray(beta, dtype=np.float64), 0.0)
+    alpha = np.empty(n)
+    for i0 in range(0, n, chunk):
+        blk = rows(i0, min(n, i0 + chunk))
+        alpha[i0:i0 + blk.shape[0]] = np.minimum(0.0, np.min(blk - b1[None, :], axis=1) - lam)
+    b2 = np.zeros(m)
+    for i0 in range(0, n, chunk):
+        blk = rows(i0, min(n, i0 + chunk))
+        b2 = np.minimum(b2, np.min(blk - alpha[i0:i0 + blk.shape[0], None], axis=0) - lam)
+    return float(np.dot(r, alpha) + np.dot(c, b2) + s * lam)
 
 
 def extended_ot_lp(C, r, c, s, A_corner=None):

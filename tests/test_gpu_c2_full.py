@@ -13,14 +13,16 @@ same size on quantities it computes in one pass:
 * the oracle's FP64 rounding applied to the GPU's duals gives the same
   rounding factors (alpha, beta to 1e-9) and cost (1e-9 relative);
 * the dense FP64 plan written by the GPU is exactly feasible and its
-  <C, X> is the reported cost.
+  <C, X> is the reported cost;
+* the whole Definition 1 check of tests/gpu_common.py, with the optimum
+  bounded by weak duality from the GPU's duals (no LP at this size).
 """
 import numpy as np
 import pytest
 
 from oracle import potref as O
 from paper_2601_17196_amd import instances as I
-from tests.gpu_common import feasible, rel
+from tests.gpu_common import check_definition1, feasible, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -53,3 +55,5 @@ def test_c2_full_size_through_the_oracle():
     X = out.plan.cpu().numpy()
     assert feasible(X, inst.r, inst.c, inst.s)
     assert rel(float(np.sum(C * X)), res["cost"]) <= 1e-12
+    info = check_definition1(inst, "f32", "aspot", out, lp_key=None)
+    print(f"c2 Definition 1: {info}", flush=True)

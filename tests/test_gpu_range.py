@@ -14,7 +14,8 @@ import pytest
 
 from oracle import potref as O
 from paper_2601_17196_amd import instances as I
-from tests.gpu_common import feasible, gpu_solve, oracle_cost_matrix, rel
+from tests.gpu_common import (check_definition1, check_definition1_batched, feasible, gpu_solve,
+                              oracle_cost_matrix, rel, tally)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,10 +72,12 @@ def test_solve_converges_like_the_oracle():
     assert feasible(out.plan.cpu().numpy(), inst.r, inst.c, inst.s)
     print(f"iterations gpu {res['iters']} oracle {ref.iters}; cost gpu {res['cost']:.9e} "
           f"oracle {ref.rounded['cost']:.9e}", flush=True)
+    check_definition1(inst, "f32", "aspot", out, lp_key="tight512:f32")
     if res["iters"] == ref.iters:
+        tally("strict", "range-tight512")
         assert rel(res["cost"], ref.rounded["cost"]) <= 1e-6
     else:
-        assert abs(res["cost"] - ref.rounded["cost"]) <= inst.eps
+        tally("def1", f"range-tight512 ({res['iters']} vs {ref.iters} iterations)")
 
 
 def _batched(inst, **kw):
@@ -83,9 +86,9 @@ def _batched(inst, **kw):
     from paper_2601_17196_amd import pot
     d = pot.to_device_instance(inst, "cuda:0", kind="f32")
     prob = dict(r=d["r"], c=d["c"], s=d["s"], C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0)
-    st, res, _ = pot.solve_batched([prob], inst.eps, algo=pot.ASPOT, step_rule=1, **kw)
+    st, res, fg = pot.solve_batched([prob], inst.eps, algo=pot.ASPOT, step_rule=1, want_uv=True, **kw)
     torch.cuda.synchronize()
-    return st, res[0]
+    return st, res[0], fg[0]
 
 
 def test_batched_lone_member_follows_the_single_solve():
@@ -93,14 +96,13 @@ def test_batched_lone_member_follows_the_single_solve():
     n m) carries the same range: it converges with the single solve."""
     inst = _inst()
     print("range: batched, one member", flush=True)
-    st, r = _batched(inst, member_elems=512 * 512)
+    st, r, fguv = _batched(inst, member_elems=512 * 512)
     one = gpu_solve(inst, "f32", "aspot", step_rule=1).result
     assert st == 0 and r["status"] == 0
     print(f"iterations batched {r['iters']} single {one['iters']}", flush=True)
+    check_definition1_batched(inst, "f32", "aspot", r, *fguv, lp_key="tight512:f32")
     if r["iters"] == one["iters"]:
         assert rel(r["cost"], one["cost"]) <= 1e-6
-    else:
-        assert abs(r["cost"] - one["cost"]) <= inst.eps
 
 
 def test_batched_group_reports_the_range_limit():
@@ -110,5 +112,5 @@ def test_batched_group_reports_the_range_limit():
     from paper_2601_17196_amd import pot
     inst = _inst()
     print("range: batched, group of members", flush=True)
-    st, r = _batched(inst, member_elems=1 << 15)
+    st, r, _ = _batched(inst, member_elems=1 << 15)
     assert r["status"] == pot.ERR_NUMERIC

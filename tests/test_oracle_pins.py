@@ -12,7 +12,7 @@ from scipy.optimize import minimize
 from scipy.special import logsumexp
 
 from paper_2601_17196_amd import instances as I
-from tests.lp_pot import assignment_brute_force, extended_ot_lp, in_polytope, pot_lp
+from tests.lp_pot import assignment_brute_force, dual_lower_bound, extended_ot_lp, in_polytope, pot_lp
 
 
 def _tiny(n, m, seed, mass_r=1.0, mass_c=1.2, s_frac=0.8, dirichlet=1.0, d=2):
@@ -33,6 +33,29 @@ def test_lp_helpers_agree(seed):
     v2 = extended_ot_lp(C, r, c, s)
     assert abs(v1 - v2) <= 1e-9
     assert in_polytope(X, r, c, s, rtol=1e-8)
+
+
+# The weak-duality bound used to certify Definition 1 where no LP can be
+# solved: exact at the LP's own optimal duals, never above the optimum for any
+# duals, the same whether C comes whole or by rows, and within eps of the
+# rounded plan's cost at the entropic duals of a converged ASPOT solve.
+@pytest.mark.parametrize("seed", range(6))
+def test_dual_lower_bound(oracle, seed):
+    n, m = 3 + seed % 5, 4 + (seed * 3) % 5
+    C, r, c, s = _tiny(n, m, seed)
+    v, X, (al, be, lam) = pot_lp(C, r, c, s, duals=True)
+    assert abs(dual_lower_bound(C, r, c, s, be, lam) - v) <= 1e-9
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        b = rng.normal(0.0, 0.5, m)
+        la = float(rng.normal(0.0, 0.5))
+        lb = dual_lower_bound(C, r, c, s, b, la)
+        assert lb <= v + 1e-12
+        assert lb == dual_lower_bound(lambda i0, i1: C[i0:i1], r, c, s, b, la, chunk=2)
+    sol = oracle.solve(C, r, c, s, 1e-2, algo="aspot", cmax=float(C.max()))
+    lb = dual_lower_bound(C, r, c, s, sol.gamma * sol.v, sol.gamma * sol.w)
+    assert lb <= v + 1e-12
+    assert sol.rounded["cost"] - lb <= 1e-2
 
 
 # ---------------------------------------------------------------------------
