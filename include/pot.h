@@ -188,6 +188,27 @@ size_t pot_workspace_bytes(const pot_problem* prob, const pot_options* opts);
 pot_status pot_solve(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
                      pot_result* res, const pot_outputs* out, void* stream);
 
+/* Size of the device array that pot_solve_noalloc uses as its workspace. */
+#define POT_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pot_solve
+ * with its workspace in a device array that the library holds for each GPU
+ * it runs on (POT_NOALLOC_SCRATCH_BYTES bytes, held until the process ends).
+ * The caller still passes every input and output.  It behaves as pot_solve
+ * with POT_FLAG_ASYNC: `res` is a DEVICE pointer to a pot_result written when
+ * the stream reaches the end of the solve, max_iter must be given
+ * (1 .. 2^20), out->w must be NULL, and validation of r, c, s, eps and the
+ * cost happens on the device.  Every kernel is launched directly (no graph is
+ * instantiated), and the call makes no allocation of any kind.  A problem
+ * whose workspace (pot_workspace_bytes) exceeds the array returns
+ * POT_ERR_WORKSPACE before any work is enqueued.  Every call on one GPU uses
+ * that GPU's array, which keeps the last call's contents (each solve writes
+ * every word it reads first): calls on one GPU must be ordered on one stream;
+ * calls that overlap (other streams, other threads) race. */
+pot_status pot_solve_noalloc(const pot_problem* prob, const pot_options* opts, pot_result* res,
+                             const pot_outputs* out, void* stream);
+
 /* Warm starts of a batch (pot_solve_batched). */
 typedef struct {
     const double* const* u0;   /* host array of `batch` device pointers to u0 (n_k each), entries may be NULL */

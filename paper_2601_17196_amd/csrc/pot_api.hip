@@ -474,6 +474,33 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     return (pot_status)hc.status;
 }
 
+// ---------------------------------------------------------------------------
+// the solve that allocates nothing: its workspace is a file-scope device
+// array, one per GPU, reached through the address the runtime reports for it
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[POT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's copy of `scratch` (looked up once per
+// device, with that device current).
+static pot_status scratch_ptr(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(POT_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(POT_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return POT_OK;
+}
+
 }  // namespace pot
 
 using namespace pot;
@@ -762,6 +789,25 @@ pot_status pot_solve(const pot_problem* prob, const pot_options* opts, void* ws,
                      pot_result* res, const pot_outputs* out, void* stream) {
     try {
         return solve_one(prob, opts, ws, ws_bytes, res, out, (hipStream_t)stream);
+    } catch (...) {
+        return fail(POT_ERR_DEVICE, "internal error");
+    }
+}
+
+pot_status pot_solve_noalloc(const pot_problem* prob, const pot_options* opts, pot_result* res,
+                             const pot_outputs* out, void* stream) {
+    try {
+        if (!prob || prob->n < 1 || prob->m < 1) return fail(POT_ERR_INVALID_ARG, "n and m must be >= 1");
+        if (!opts) return fail(POT_ERR_INVALID_ARG, "null options");
+        const size_t need = layout(prob, geometry(prob, opts), nullptr, nullptr);
+        if (need > (size_t)POT_NOALLOC_SCRATCH_BYTES)
+            return fail(POT_ERR_WORKSPACE, "the problem needs more scratch than pot_solve_noalloc holds "
+                                           "(POT_NOALLOC_SCRATCH_BYTES)");
+        void* ptr = nullptr;
+        pot_status ps = scratch_ptr(&ptr);
+        if (ps != POT_OK) return ps;
+        return solve_one(prob, opts, ptr, (size_t)POT_NOALLOC_SCRATCH_BYTES, res, out, (hipStream_t)stream,
+                         /*force_async=*/true, /*direct=*/true);
     } catch (...) {
         return fail(POT_ERR_DEVICE, "internal error");
     }

@@ -28,6 +28,7 @@ COST_F32, COST_BF16, COST_POINTS = 0, 1, 3
 FLAG_WANT_PLAN, FLAG_NO_ROUND, FLAG_NO_GRAPH, FLAG_ASYNC = 1, 2, 4, 8
 
 OK, ERR_INVALID_ARG, ERR_NO_CONVERGENCE, ERR_NUMERIC, ERR_DEVICE, ERR_WORKSPACE, ERR_UNSUPPORTED = range(7)
+NOALLOC_SCRATCH_BYTES = 32 << 20   # POT_NOALLOC_SCRATCH_BYTES
 
 
 class PotError(RuntimeError):
@@ -119,6 +120,9 @@ def load():
     lib.pot_warm_predict.argtypes = [ct.c_int32, ct.POINTER(WarmInstance), ct.c_double, ct.c_void_p, ct.c_void_p,
                                      ct.c_size_t, ct.c_void_p]
     lib.pot_warm_predict.restype = ct.c_int
+    lib.pot_solve_noalloc.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.POINTER(Result),
+                                      ct.POINTER(Outputs), ct.c_void_p]
+    lib.pot_solve_noalloc.restype = ct.c_int
     lib.pot_time_pass.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
                                   ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.c_void_p]
     lib.pot_time_pass.restype = ct.c_int
