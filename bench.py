@@ -1,14 +1,30 @@
-"""Benchmark: POT solves/s at eps = 1e-2 on one MI355X.
+"""Benchmark: POT solves/s at eps = 1e-2 on one MI355X, warm-started and
+batched ASPOT against cold batched and plain ASPOT.
 
-A step is one whole solve through the C ABI (pot_solve): setup
-("Approximating POT"), the ASPOT loop (three fused statistics passes per
-iteration with the on-device decisions), the FP64 rounding onto U(r, c, s)
-and the objective.  Inputs are resident in HBM before the timed region.
+A step is one batch of 1024 POT instances (n = m = 256, 2-D Gaussian
+mixtures with 2-5 components, Dirichlet(0.5) masses with totals in
+[0.8, 1.2], s uniform in [0.5, 0.9] x the smaller mass, squared-Euclidean
+cost normalised to max 1, stored dense in FP32, eps = 1e-2): the warm-start
+network's inference kernels predict every instance's duals, then one
+persistent launch of pot_solve_batched runs, for all 1024 instances, the
+setup of Algorithm 2, the warm-start check (the prediction is kept only if
+it lowers phi), the ASPOT loop and the FP64 rounding onto U(r, c, s).  value =
+1024 x steps / elapsed time of the timed steps (HIP events), inputs resident
+in HBM.  Beside it, in `extra`: the same batch cold (batched), plain cold
+pot_solve calls one after another (a sample), the 512-instance uneven batch,
+the single 4096^2 instance (streamed FP32 / BF16 cost, recomputed points
+cost), the 20000^2 instance's HBM roofline (FP32 and BF16) and the other
+solver options.
 
-Default workload: one instance, n = m = 4096, 3-D points in 8 Gaussian
-clusters (sigma 0.05) with 10 % uniform outliers, squared-Euclidean cost
-normalised to max 1 and stored dense in FP32, uniform masses with totals
-1.0 / 1.0, s = 0.9, eps = 1e-2, cold start.
+Rooflines.  The headline's dominant kernel is the persistent batched kernel:
+its work is n m exponentials per statistics pass (three passes per ASPOT
+iteration), bound by the vector ALU (each 256-column C5 row costs about 14
+VALU instructions per element, the exponential at a quarter rate, which
+gives the peak BATCHED_PEAK_GELEM below at 256 CUs x 64 lanes x 2.4 GHz).
+The single-instance tile kernel streams C and is bound by HBM (8 TB/s).
+Kernel times come from HIP events recorded around each launch on the stream
+it runs on (medians of >= 10 launches after 3 warm-ups); the committed
+rocprofv3 summaries under profiles/ give the same kernels' durations.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -25,17 +41,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Vector-ALU ceilings in G elements/s: 256 CUs x 64 lanes x 2.4 GHz =
+# 3.93e13 lane-instructions/s, divided by the issue cost of one element of the
+# statistics pass in the compiled inner loops (the exponential counts 4: it
+# issues at a quarter rate).  Batched 256-column rows: 14.19 VALU incl. the
+# exponential -> 17.19; tile kernel, points cost (d = 3): 12.44 -> 15.44.
+ALU_LANE_OPS = 256 * 64 * 2.4e9
+BATCHED_PEAK_GELEM = ALU_LANE_OPS / 17.19 / 1e9
+POINTS_PEAK_GELEM = ALU_LANE_OPS / 15.44 / 1e9
 COPY_BYTES = 256 << 20          # the plain copy of the counter-scale probe (bytes read, and written)
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "stats_pass_c2_4096_f32_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the tile kernel from the committed counter
-    summary, or None when it is missing or was taken on other kernel sources."""
-    if not os.path.exists(PMC_SUMMARY):
+def measured_traffic(name):
+    """HBM bytes per launch of a kernel from a committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
         return None
     from paper_2601_17196_amd import profile_summary as PS
-    s = json.load(open(PMC_SUMMARY))
+    s = json.load(open(path))
     if s.get("kernel_source_hash") != PS.kernel_source_hash():
         return None
     return s.get("traffic_bytes")
@@ -52,31 +77,22 @@ def _build_if_missing():
         __graft_entry__.build()
 
 
-def run_solve(pot, d, eps, algo, kind, **kw):
-    if kind == "points":
-        return pot.solve(d["r"], d["c"], d["s"], eps, x=d["x"], y=d["y"], cost_scale=d["cost_scale"],
-                         cmax=1.0, algo=algo, **kw)
-    return pot.solve(d["r"], d["c"], d["s"], eps, C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0,
-                     algo=algo, **kw)
+def _median(xs):
+    xs = sorted(xs)
+    k = len(xs)
+    return xs[k // 2] if k % 2 else 0.5 * (xs[k // 2 - 1] + xs[k // 2])
 
 
-def time_solves(pot, d, eps, algo, kind, steps, warmup, workspace, **kw):
+def _event_ms(fn):
+    """(ms of fn's GPU work on the current stream, fn's return value)."""
     import torch
-    for _ in range(warmup):
-        run_solve(pot, d, eps, algo, kind, workspace=workspace, want_factors=False, **kw)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
     e0.record()
-    outs = []
-    for _ in range(steps):
-        outs.append(run_solve(pot, d, eps, algo, kind, workspace=workspace, want_factors=False, **kw))
+    out = fn()
     e1.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = e0.elapsed_time(e1)
-    return outs, wall, ev_ms
+    return e0.elapsed_time(e1), out
 
 
 def _batch_probs(pot, insts, dev):
@@ -87,52 +103,14 @@ def _batch_probs(pot, insts, dev):
     return probs
 
 
-def _timed(fn, reps):
-    import torch
-    fn()                                   # warm-up (first call also autotunes the batched launch)
-    torch.cuda.synchronize()
-    best, out = None, None
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        out = fn()
-        e1.record()
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1)
-        best = t if best is None else min(best, t)
-    return best, out
+def _work_elems(insts, res):
+    """Statistics-pass elements of a batched ASPOT run: three passes over
+    n x m per iteration."""
+    return sum(3 * r["iters"] * i.n * i.m for i, r in zip(insts, res))
 
 
-def bench_batched(pot, I, dev, eps, reps, plain_sample):
-    """The uneven batch (512 instances, n, m log-uniform in [64, 1024]):
-    pot_solve_batched against sequential pot_solve calls on a sample."""
-    import numpy as np
-    import torch
-    insts = I.c4_batch(512)
-    probs = _batch_probs(pot, insts, dev)
-    ws = torch.empty(pot.workspace_bytes_batched(probs) + 512, dtype=torch.uint8, device=dev)
-    t, (st, res, _) = _timed(lambda: pot.solve_batched(probs, eps, workspace=ws, want_duals=False), reps)
-    its = np.array([r["iters"] for r in res])
-    ok = all(r["status"] == 0 for r in res)
-    sample = list(range(0, len(insts), len(insts) // plain_sample))[:plain_sample]
-
-    def plain():
-        for j in sample:
-            pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0, want_factors=False)
-    tp, _ = _timed(plain, 1)
-    out = {"instances": len(insts), "solves_per_s": len(insts) / (t / 1e3), "ms": t, "all_ok": ok,
-           "iters_median": float(np.median(its)), "iters_max": int(its.max()),
-           "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample)}
-    del ws, probs
-    torch.cuda.empty_cache()
-    return out
-
-
-def bench_warm(pot, I, dev, eps, reps, plain_sample):
-    """The learned warm start on the n = m = 256 mixture batch (1024
-    instances): inference + warm-started batched ASPOT against cold batched
-    ASPOT and sequential plain solves (sample)."""
+def headline(pot, I, dev, eps, steps, warmup, plain_sample, cold_reps):
+    """C5: warm-started batched ASPOT (the metric), cold batched, plain."""
     import numpy as np
     import torch
     insts = I.c5_batch(1024)
@@ -141,77 +119,260 @@ def bench_warm(pot, I, dev, eps, reps, plain_sample):
                 y=torch.from_numpy(np.ascontiguousarray(i.y, dtype=np.float32)).to(dev),
                 r=p["r"], c=p["c"], cost_scale=i.cost_scale) for i, p in zip(insts, probs)]
     ws = torch.empty(pot.workspace_bytes_batched(probs) + 512, dtype=torch.uint8, device=dev)
+    wws = torch.empty(pot.load().pot_warm_workspace_bytes(len(pts)) + 512, dtype=torch.uint8, device=dev)
     blob = pot.warm_blob(device=dev)
+    t_inf, t_bat, last = [], [], {}
 
-    def warm():
-        preds = pot.warm_predict(pts, eps, blob)
-        return pot.solve_batched(probs, eps, u0=[p[0] for p in preds], v0=[p[1] for p in preds],
-                                 w0=[0.0] * len(preds), warm_check=True, workspace=ws, want_duals=False)
-    tc, (stc, resc, _) = _timed(lambda: pot.solve_batched(probs, eps, workspace=ws, want_duals=False), reps)
-    tw, (stw, resw, _) = _timed(warm, reps)
-    ti, _ = _timed(lambda: pot.warm_predict(pts, eps, blob), reps)
+    def step():
+        # inference, then the batched solve, each bracketed by events on the stream it runs on
+        ti, preds = _event_ms(lambda: pot.warm_predict(pts, eps, blob, workspace=wws))
+        tb, out = _event_ms(lambda: pot.solve_batched(
+            probs, eps, u0=[p[0] for p in preds], v0=[p[1] for p in preds], w0=[0.0] * len(preds),
+            warm_check=True, workspace=ws, want_duals=False))
+        t_inf.append(ti)
+        t_bat.append(tb)
+        last["res"] = out[1]
+        last["st"] = out[0]
+
+    for _ in range(warmup):
+        step()
+    t_inf.clear()
+    t_bat.clear()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    resw = last["res"]
+    log(f"warm+batched: {steps} steps in {ms:.1f} ms (wall {wall * 1e3:.1f}); batched launch median "
+        f"{_median(t_bat):.1f} ms, inference median {_median(t_inf):.2f} ms")
+    # cold batched (the same launch without warm starts) and plain sequential solves
+    tc = []
+    for k in range(cold_reps + 1):
+        t, out = _event_ms(lambda: pot.solve_batched(probs, eps, workspace=ws, want_duals=False))
+        if k > 0:
+            tc.append(t)
+    resc = out[1]
+    sample = list(range(0, len(insts), len(insts) // plain_sample))[:plain_sample]
+    pot.solve(probs[0]["r"], probs[0]["c"], probs[0]["s"], eps, C=probs[0]["C"], cmax=1.0, want_factors=False)
+
+    def plain():
+        for j in sample:
+            pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0,
+                      want_factors=False)
+    tp, _ = _event_ms(plain)
+    itw = np.array([r["iters"] for r in resw])
+    itc = np.array([r["iters"] for r in resc])
+    elems = _work_elems(insts, resw)
+    med_b = _median(t_bat)
+    achieved = elems / (med_b * 1e-3) / 1e9
+    roof = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(BATCHED_PEAK_GELEM, 1),
+            "unit": "Gelem/s", "frac": round(achieved / BATCHED_PEAK_GELEM, 4),
+            "traffic": measured_traffic("batched_c5_1024x256_traffic.json")}
+    info = {
+        "instances": len(insts),
+        "warm_batched_solves_per_s": len(insts) * steps / (ms / 1e3),
+        "cold_batched_solves_per_s": len(insts) / (_median(tc) / 1e3),
+        "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample),
+        "batched_launch_ms_median": med_b, "inference_ms_median": _median(t_inf),
+        "cold_batched_launch_ms_median": _median(tc),
+        "warm_kept": int(sum(r["used_warm"] for r in resw)),
+        "iters_median_warm": float(np.median(itw)), "iters_median_cold": float(np.median(itc)),
+        "iters_max_warm": int(itw.max()), "iters_max_cold": int(itc.max()),
+        "iters_total_warm": int(itw.sum()), "iters_total_cold": int(itc.sum()),
+        "statistics_elements_per_launch": elems,
+        "all_ok": last["st"] == 0 and all(r["status"] == 0 for r in resw) and all(r["status"] == 0 for r in resc),
+        "max_E_over_tol": float(max(r["E"] / r["tol"] for r in resw)),
+    }
+    del ws, probs, pts
+    torch.cuda.empty_cache()
+    return ms / steps, info, roof, insts, itc
+
+
+def cpu_baseline(insts, iters_cold, eps, per_inst_iters=150, sample=6):
+    """The FP64 oracle (as it stands) on the host cores, on a bounded sample
+    of the headline workload: `per_inst_iters` ASPOT iterations on each of
+    `sample` instances of the batch (all n = m = 256), whose per-iteration
+    time, times the batch's total cold iteration count, gives the oracle's
+    solves/s for the batch."""
+    import numpy as np
+
+    from oracle import potref
+    cores = potref.threads()
+    tot_t, tot_it = 0.0, 0
+    for inst in insts[:sample]:
+        C = inst.C32.astype(np.float64)
+        gam, tol, M, rt, ct_ = potref.setup(inst.r, inst.c, inst.s, eps, cmax=1.0)
+        t0 = time.perf_counter()
+        _, _, _, it, _, _, _ = potref.aspot(C, gam, tol, rt, ct_, inst.s, M, max_iter=per_inst_iters)
+        tot_t += time.perf_counter() - t0
+        tot_it += it
+    per_iter = tot_t / tot_it
+    total = float(np.sum(iters_cold))
+    return {"value": len(insts) / (per_iter * total), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{tot_it} ASPOT iterations over the first {sample} instances of the batch (n = m = 256, "
+                       f"{tot_t:.1f} s, {per_iter * 1e3:.2f} ms/iteration), scaled by the batch's "
+                       f"{int(total)} cold iterations")}
+
+
+def tile_roofline(pot, d, eps, u0, v0, w0, nbytes, reps, kind="f32", traffic=None, points=False, elems=None):
+    """Median tile-kernel time (HIP events around each launch, 3 warm-ups)
+    of the statistics pass at the given duals, and its roofline."""
+    kw = dict(u0=u0, v0=v0, w0=w0)
+    if points:
+        ms, fin = pot.time_pass(d["r"], d["c"], d["s"], eps, reps=reps, x=d["x"], y=d["y"],
+                                cost_scale=d["cost_scale"], cmax=1.0, **kw)
+        ach = elems / (ms * 1e-3) / 1e9
+        return ms, fin, {"bound": "alu", "achieved": round(ach, 1), "peak": round(POINTS_PEAK_GELEM, 1),
+                         "unit": "Gelem/s", "frac": round(ach / POINTS_PEAK_GELEM, 4), "traffic": None}
+    ms, fin = pot.time_pass(d["r"], d["c"], d["s"], eps, reps=reps, C=d["C"], kind=d["kind"], ldc=d["ldc"],
+                            cmax=d.get("cmax_given", 1.0), **kw)
+    ach = nbytes / (ms * 1e-3) / 1e9
+    return ms, fin, {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+
+def time_solves(pot, fn, steps, warmup=1):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ms, outs = _event_ms(lambda: [fn() for _ in range(steps)])
+    return steps / (ms / 1e3), outs[-1]
+
+
+def bench_c2(pot, I, dev, eps, reps):
+    """The single 4096^2 instance (3-D clusters + outliers, s = 0.9): plain
+    cold solves with the streamed FP32 / BF16 cost and the recomputed points
+    cost, the solver options, and the tile kernel's roofline."""
+    import torch
+    inst = I.c2(0, n=4096)
+    out = {}
+    for kind in ("f32", "bf16", "points"):
+        d = pot.to_device_instance(inst, dev, kind=kind)
+        if kind == "points":
+            fn = lambda: pot.solve(d["r"], d["c"], d["s"], eps, x=d["x"], y=d["y"], cost_scale=d["cost_scale"],
+                                   cmax=1.0, want_factors=False)
+        else:
+            fn = lambda: pot.solve(d["r"], d["c"], d["s"], eps, C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0,
+                                   want_factors=False)
+        sps, o = time_solves(pot, fn, 10 if kind == "f32" else 3)
+        nb = inst.n * inst.m * {"f32": 4, "bf16": 2, "points": 0}[kind]
+        ms, fin, roof = tile_roofline(pot, d, eps, o.u, o.v, o.w, nb, reps, kind=kind, points=kind == "points",
+                                      elems=inst.n * inst.m,
+                                      traffic=measured_traffic("stats_pass_c2_4096_f32_traffic.json")
+                                      if kind == "f32" else None)
+        out[f"aspot_{kind}"] = {"solves_per_s": sps, "iters": o.result["iters"], "cost": o.result["cost"],
+                                "us_per_iteration": 1e6 / sps / max(o.result["iters"], 1),
+                                "tile_kernel_us": ms * 1e3, "fin_kernel_us": fin * 1e3, "roofline": roof}
+        log(f"c2 {kind}: {out[f'aspot_{kind}']}")
+        if kind == "f32":
+            f32 = d
+            base_cost = o.result["cost"]
+        else:
+            del d
+    d = f32
+    sps, o = time_solves(pot, lambda: pot.solve(d["r"], d["c"], d["s"], eps, C=d["C"], cmax=1.0, algo=pot.SINKHORN,
+                                               want_factors=False), 5)
+    out["sinkhorn_f32"] = {"solves_per_s": sps, "iters": o.result["iters"], "cost": o.result["cost"]}
+    sps, o = time_solves(pot, lambda: pot.solve(d["r"], d["c"], d["s"], eps, C=d["C"], cmax=1.0, algo=pot.SINKHORN,
+                                               gamma_rule=1, p=2.0, want_factors=False), 5)
+    out["sinkhorn_tuned_p2"] = {"solves_per_s": sps, "iters": o.result["iters"], "cost": o.result["cost"],
+                                "gamma": o.result["gamma"], "cost_minus_aspot": o.result["cost"] - base_cost}
+    for name, kw in (("aspot_step_rule1", dict(step_rule=1)), ("aspot_block_rule1", dict(block_rule=1))):
+        sps, o = time_solves(pot, lambda: pot.solve(d["r"], d["c"], d["s"], eps, C=d["C"], cmax=1.0,
+                                                   want_factors=False, **kw), 2)
+        out[name] = {"solves_per_s": sps, "iters": o.result["iters"], "cost_minus_canonical": o.result["cost"] - base_cost}
+    log(f"c2 options: { {k: out[k] for k in ('sinkhorn_f32', 'sinkhorn_tuned_p2', 'aspot_step_rule1', 'aspot_block_rule1')} }")
+    del d, f32
+    torch.cuda.empty_cache()
+    return out
+
+
+def _device_cost(inst, dtype, dev):
+    import numpy as np
+    import torch
+    x = torch.from_numpy(inst.x.astype(np.float64)).to(dev)
+    y = torch.from_numpy(inst.y.astype(np.float64)).to(dev)
+    C = torch.empty((inst.n, inst.m), dtype=torch.float32 if dtype == "f32" else torch.bfloat16, device=dev)
+    for i0 in range(0, inst.n, 2048):
+        xb = x[i0:i0 + 2048]
+        D = torch.zeros((xb.shape[0], inst.m), dtype=torch.float64, device=dev)
+        for k in range(x.shape[1]):
+            diff = xb[:, k:k + 1] - y[None, :, k]
+            D += diff * diff
+        C[i0:i0 + 2048] = (D * inst.cost_scale).to(C.dtype)
+    return C if dtype == "f32" else C.view(torch.int16)
+
+
+def bench_c3(pot, I, dev, eps, reps):
+    """The 20000^2 instance: one solve per cost type for its converged duals,
+    then the tile kernel timed there (HBM roofline: n m x bytes per element
+    per launch), and the solve time."""
+    import torch
+    inst = I.c3(0, dense=False)
+    r = torch.from_numpy(inst.r).to(dev)
+    c = torch.from_numpy(inst.c).to(dev)
+    out = {}
+    for kind in ("f32", "bf16"):
+        C = _device_cost(inst, kind, dev)
+        k = pot.COST_F32 if kind == "f32" else pot.COST_BF16
+        fn = lambda: pot.solve(r, c, inst.s, eps, C=C, kind=k, ldc=inst.m, cmax=0.0, want_factors=False)
+        sps, o = time_solves(pot, fn, 2)
+        d = {"r": r, "c": c, "s": inst.s, "C": C, "kind": k, "ldc": inst.m, "cmax_given": o.result["cmax"]}
+        nb = inst.n * inst.m * (4 if kind == "f32" else 2)
+        ms, fin, roof = tile_roofline(pot, d, eps, o.u, o.v, o.w, nb, reps, kind=kind,
+                                      traffic=measured_traffic(f"stats_pass_c3_20000_{kind}_traffic.json"))
+        out[kind] = {"solves_per_s": sps, "iters": o.result["iters"], "tile_kernel_us": ms * 1e3,
+                     "fin_kernel_us": fin * 1e3, "roofline": roof}
+        log(f"c3 {kind}: {out[kind]}")
+        del C, d
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_c4(pot, I, dev, eps, reps, plain_sample):
+    """The uneven batch (512 instances, n, m log-uniform in [64, 1024])."""
+    import numpy as np
+    import torch
+    insts = I.c4_batch(512)
+    probs = _batch_probs(pot, insts, dev)
+    ws = torch.empty(pot.workspace_bytes_batched(probs) + 512, dtype=torch.uint8, device=dev)
+    ts = []
+    for k in range(reps + 1):
+        t, (st, res, _) = _event_ms(lambda: pot.solve_batched(probs, eps, workspace=ws, want_duals=False))
+        if k > 0:
+            ts.append(t)
+    its = np.array([r["iters"] for r in res])
     sample = list(range(0, len(insts), len(insts) // plain_sample))[:plain_sample]
 
     def plain():
         for j in sample:
             pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0, want_factors=False)
-    tp, _ = _timed(plain, 1)
-    itc = np.array([r["iters"] for r in resc])
-    itw = np.array([r["iters"] for r in resw])
-    out = {"instances": len(insts),
-           "warm_batched_solves_per_s": len(insts) / (tw / 1e3),
-           "cold_batched_solves_per_s": len(insts) / (tc / 1e3),
-           "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample),
-           "inference_ms": ti, "warm_kept": int(sum(r["used_warm"] for r in resw)),
-           "iters_median_warm": float(np.median(itw)), "iters_median_cold": float(np.median(itc)),
-           "iters_total_warm": int(itw.sum()), "iters_total_cold": int(itc.sum()),
-           "max_cost_gap_warm_vs_cold": float(max(abs(a["cost"] - b["cost"]) for a, b in zip(resw, resc))),
-           "all_ok": all(r["status"] == 0 for r in resw) and all(r["status"] == 0 for r in resc)}
-    del ws, probs, pts
+    tp, _ = _event_ms(plain)
+    t = _median(ts)
+    ach = _work_elems(insts, res) / (t * 1e-3) / 1e9
+    out = {"instances": len(insts), "solves_per_s": len(insts) / (t / 1e3), "ms_median": t,
+           "all_ok": all(r["status"] == 0 for r in res), "iters_median": float(np.median(its)),
+           "iters_max": int(its.max()), "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample),
+           "roofline": {"bound": "alu", "achieved": round(ach, 1), "peak": round(BATCHED_PEAK_GELEM, 1),
+                        "unit": "Gelem/s", "frac": round(ach / BATCHED_PEAK_GELEM, 4), "traffic": None}}
+    del ws, probs
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(inst, iters_full, eps, budget_iters, one_core_iters=2):
-    """The FP64 oracle (as it stands) timed on the host cores on a bounded
-    sample: `budget_iters` ASPOT iterations of the same instance, scaled to
-    solves/s with the full solve's iteration count; then `one_core_iters`
-    iterations on one thread."""
-    import numpy as np
-
-    from oracle import potref
-    C = inst.C32.astype(np.float64)
-    gam, tol, M, rt, ct_ = potref.setup(inst.r, inst.c, inst.s, eps, cmax=1.0)
-    cores = potref.threads()
-    t0 = time.perf_counter()
-    potref.aspot(C, gam, tol, rt, ct_, inst.s, M, max_iter=budget_iters)
-    dt = time.perf_counter() - t0
-    per_iter = dt / budget_iters
-    potref.set_threads(1)
-    t0 = time.perf_counter()
-    potref.aspot(C, gam, tol, rt, ct_, inst.s, M, max_iter=one_core_iters)
-    dt1 = time.perf_counter() - t0
-    potref.set_threads(cores)
-    per_iter1 = dt1 / one_core_iters
-    return {
-        "value": 1.0 / (per_iter * iters_full),
-        "unit": "solves/s",
-        "cores": cores,
-        "kind": "oracle",
-        "sample": (f"{budget_iters} ASPOT iterations of the same n=m={inst.n} instance "
-                   f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration), scaled by the full solve's "
-                   f"{iters_full} iterations; on 1 core {one_core_iters} iterations "
-                   f"({per_iter1 * 1e3:.0f} ms/iteration)"),
-        "value_1core": 1.0 / (per_iter1 * iters_full),
-    }
-
-
-def bench_shard(pot, I, dev, eps):
+def bench_shard(pot, I, dev, eps, reps):
     """The statistics pass on one GPU's share of the 20000^2 instance split by
-    rows over 8 GPUs: rows 0..2499 of its cost against all 20000 columns
-    (FP32, the same normalisation), solved as an instance of its own (source
-    masses rescaled to total 1, s = 0.7) to get representative duals, then
-    the pass timed at them."""
+    rows over 8 GPUs: rows 0..2499 against all 20000 columns (FP32), solved as
+    an instance of its own (source masses rescaled to total 1, s = 0.7) to get
+    representative duals, then the pass timed at them."""
     import numpy as np
     import torch
     inst = I.c3(0, dense=False)
@@ -227,7 +388,7 @@ def bench_shard(pot, I, dev, eps):
     r = torch.full((ns,), 1.0 / ns, dtype=torch.float64, device=dev)
     c = torch.from_numpy(inst.c).to(dev)
     o = pot.solve(r, c, 0.7, eps, C=C, cmax=1.0, want_factors=False)
-    ms = pot.time_pass(r, c, 0.7, eps, reps=20, C=C, cmax=1.0, u0=o.u, v0=o.v, w0=o.w)[0]
+    ms = pot.time_pass(r, c, 0.7, eps, reps=reps, C=C, cmax=1.0, u0=o.u, v0=o.v, w0=o.w)[0]
     gbs = ns * m * 4 / (ms * 1e-3) / 1e9
     nx, ny = (m + 255) // 256, (ns + 127) // 128
     return {"n": ns, "m": m, "iters": o.result["iters"], "tile_kernel_us": ms * 1e3, "GB_per_s": gbs,
@@ -235,22 +396,52 @@ def bench_shard(pot, I, dev, eps):
             "allreduce_bytes_per_pass": (m + 3) * 8}
 
 
+def bench_register(pot, dev, eps, n=4096):
+    """Rigid registration through POT (Section 4): X = n 3-D points in four
+    Gaussian blobs, Y = half of them moved by a rigid map; alpha = 0.4,
+    gamma0 = 4.4e-3 annealed by 0.83 per registration.  Warm starts from the
+    previous registration's duals against cold starts: registrations,
+    iterations and time."""
+    import numpy as np
+    import torch
+    g = np.random.default_rng(3)
+    centres = np.array([[0.0, 0.0, 0.0], [0.5, 0.2, 0.1], [1.0, 0.5, 0.0], [1.4, 1.0, 0.3]])
+    X = (centres[g.integers(0, 4, n)] + 0.08 * g.standard_normal((n, 3))).astype(np.float32)
+    idx = g.permutation(n)[: n // 2]
+    a = np.array([0.2, 1.0, 0.4]) / np.linalg.norm([0.2, 1.0, 0.4])
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    R0 = np.eye(3) + np.sin(0.5) * K + (1 - np.cos(0.5)) * K @ K
+    t0 = np.array([0.3, -0.2, 0.15])
+    Y = ((X[idx].astype(np.float64) - t0) @ R0).astype(np.float32)
+    x, y = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    m = len(Y)
+    r = torch.full((n,), 1.0 / n, dtype=torch.float64, device=dev)
+    c = torch.full((m,), 1.0 / m, dtype=torch.float64, device=dev)
+    s = 0.4 * m / n
+    out = {"n": n, "m": m, "s": s}
+    for warm in (True, False):
+        pot.register(x, y, r, c, s, eps=eps, max_steps=2, warm=warm)            # warm-up
+        ms, o = _event_ms(lambda: pot.register(x, y, r, c, s, eps=eps, max_steps=60, warm=warm))
+        err = float(np.max(np.abs((Y.astype(np.float64) @ o.R.T + o.t) - X[idx])))
+        out["warm" if warm else "cold"] = {"registrations": o.steps, "iters_total": o.total_iters,
+                                           "iters_per_registration": [int(k) for k in o.iters], "ms": ms,
+                                           "solves_per_s": o.steps / (ms / 1e3), "alignment_error": err}
+    out["iteration_ratio_warm_over_cold"] = out["warm"]["iters_total"] / max(out["cold"]["iters_total"], 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--algo", default="aspot", choices=["aspot", "sinkhorn"])
-    ap.add_argument("--kind", default="f32", choices=["f32", "bf16", "points"])
-    ap.add_argument("--cpu-iters", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=20, help="timed launches per kernel-time median (after 3 warm-ups)")
+    ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--plain-sample", type=int, default=32)
-    ap.add_argument("--pmc-probe", action="store_true",
-                    help="profiling workload only: a 256 MiB device copy (the counters' scale), then one "
-                         "solve and 20 timed statistics passes of the default workload; prints no JSON line")
+    ap.add_argument("--pmc-probe", choices=["none", "c5", "c3f32", "c3bf16", "c2"], default="none",
+                    help="profiling workload only: a 256 MiB device copy (the counters' scale), then the named "
+                         "workload's kernel once or a few times; prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the solver has no multi-GPU path (batches would shard by "
@@ -258,7 +449,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     _build_if_missing()
@@ -267,145 +457,77 @@ def main():
 
     dev = torch.device("cuda:0")
     eps = 1e-2
-    if args.pmc_probe:
+    if args.pmc_probe != "none":
         a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    log(f"generating workload n=m={args.n}")
-    inst = I.c2(0, n=args.n)
-    d = pot.to_device_instance(inst, dev, kind=args.kind)
-    algo = pot.ASPOT if args.algo == "aspot" else pot.SINKHORN
-    first = run_solve(pot, d, eps, algo, args.kind)
-    # workspace sized once, reused by every timed solve
-    prob = pot.make_problem(d["r"], d["c"], d["s"], C=d.get("C"), x=d.get("x"), y=d.get("y"),
-                            kind=d.get("kind"), ldc=d.get("ldc"), cost_scale=d.get("cost_scale", 0.0),
-                            cmax=1.0)
-    ws = torch.empty(pot.workspace_bytes(prob, pot.make_options(eps, algo=algo)) + 256, dtype=torch.uint8,
-                     device=dev)
-    log(f"first solve: status {first.status} iters {first.result['iters']} cost {first.result['cost']:.9e}")
-    if args.pmc_probe:
-        kw = dict(u0=first.u, v0=first.v, w0=first.w)
-        if args.kind == "points":
-            pot.time_pass(d["r"], d["c"], d["s"], eps, reps=20, x=d["x"], y=d["y"], cost_scale=d["cost_scale"],
-                          cmax=1.0, **kw)
+        if args.pmc_probe == "c5":
+            headline(pot, I, dev, eps, 1, 0, 1, 0)
+        elif args.pmc_probe == "c2":
+            inst = I.c2(0, n=4096)
+            d = pot.to_device_instance(inst, dev, kind="f32")
+            o = pot.solve(d["r"], d["c"], d["s"], eps, C=d["C"], cmax=1.0)
+            pot.time_pass(d["r"], d["c"], d["s"], eps, reps=10, C=d["C"], cmax=1.0, u0=o.u, v0=o.v, w0=o.w)
         else:
-            pot.time_pass(d["r"], d["c"], d["s"], eps, reps=20, C=d["C"], kind=d["kind"], ldc=d["ldc"], cmax=1.0, **kw)
+            kind = args.pmc_probe[2:]
+            inst = I.c3(0, dense=False)
+            r = torch.from_numpy(inst.r).to(dev)
+            c = torch.from_numpy(inst.c).to(dev)
+            C = _device_cost(inst, kind, dev)
+            k = pot.COST_F32 if kind == "f32" else pot.COST_BF16
+            o = pot.solve(r, c, inst.s, eps, C=C, kind=k, ldc=inst.m, cmax=0.0)
+            pot.time_pass(r, c, inst.s, eps, reps=10, C=C, kind=k, ldc=inst.m, cmax=o.result["cmax"], u0=o.u,
+                          v0=o.v, w0=o.w)
         torch.cuda.synchronize()
         log("pmc probe done")
         return
-    outs, wall, ev_ms = time_solves(pot, d, eps, algo, args.kind, args.steps, args.warmup, ws)
-    iters = outs[-1].result["iters"]
-    ms_per_step = ev_ms / args.steps
-    value = args.steps / (ev_ms / 1e3)
-    log(f"timed {args.steps} solves: {ev_ms:.2f} ms (events), {wall * 1e3:.2f} ms (wall); "
-        f"{value:.3f} solves/s, {iters} iterations, {ms_per_step / max(iters, 1) * 1e3:.2f} us/iteration")
 
-    # roofline of the dominant kernel: the fused statistics pass at the
-    # converged duals, timed with HIP events around each dispatch
-    o = first
-    kw = dict(u0=o.u, v0=o.v, w0=o.w)
-    if args.kind == "points":
-        pass_ms, fin_ms = pot.time_pass(d["r"], d["c"], d["s"], eps, reps=50, x=d["x"], y=d["y"],
-                                        cost_scale=d["cost_scale"], cmax=1.0, **kw)
-    else:
-        pass_ms, fin_ms = pot.time_pass(d["r"], d["c"], d["s"], eps, reps=50, C=d["C"], kind=d["kind"],
-                                        ldc=d["ldc"], cmax=1.0, **kw)
-    n = m = args.n
-    elem_bytes = {"f32": 4, "bf16": 2, "points": 0}[args.kind]
-    if args.kind == "points":
-        # ALU-bound: algorithmic work = n*m exponentials per pass
-        achieved = n * m / (pass_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": None, "unit": "Texp/s", "frac": None,
-                "traffic": None}
-    else:
-        alg_bytes = n * m * elem_bytes
-        achieved = alg_bytes / (pass_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic() if args.kind == "f32" and n == 4096 else None}
-    log(f"tile kernel: {pass_ms * 1e3:.2f} us/launch -> {achieved:.1f} {roof['unit']}; "
-        f"finalising kernel {fin_ms * 1e3:.2f} us")
-
-    extra = {"iters": iters, "us_per_iteration": ms_per_step / max(iters, 1) * 1e3,
-             "tile_kernel_us": pass_ms * 1e3, "fin_kernel_us": fin_ms * 1e3,
-             "cost": outs[-1].result["cost"], "E": outs[-1].result["E"]}
+    log("headline: 1024 instances n = m = 256, learned warm start + batched ASPOT")
+    ms_step, info, roof, insts, itc = headline(pot, I, dev, eps, args.steps, args.warmup, args.plain_sample, 3)
+    value = info["instances"] / (ms_step / 1e3)
+    log(f"headline: {value:.1f} solves/s; {info}")
+    log(f"batched kernel roofline: {roof}")
+    extra = {"c5_warm_cold_plain": info}
     if not args.no_extra:
-        for name, kind2, algo2 in [("sinkhorn_f32", "f32", pot.SINKHORN), ("aspot_points", "points", pot.ASPOT),
-                                   ("aspot_bf16", "bf16", pot.ASPOT)]:
-            if kind2 == args.kind and algo2 == algo:
-                continue
-            d2 = d if kind2 == args.kind else pot.to_device_instance(inst, dev, kind=kind2)
-            o2, w2, ev2 = time_solves(pot, d2, eps, algo2, kind2, 3, 1, None)
-            extra[name] = {"solves_per_s": 3 / (ev2 / 1e3), "iters": o2[-1].result["iters"],
-                           "cost": o2[-1].result["cost"]}
-            log(f"{name}: {extra[name]}")
-            del d2
-            torch.cuda.empty_cache()
-        # the solver variants against the canonical readings (same instance)
-        if args.kind == "f32" and algo == pot.ASPOT:
-            for name, kw in [("aspot_step_rule1", dict(step_rule=1)), ("aspot_block_rule1", dict(block_rule=1))]:
-                probe = run_solve(pot, d, eps, pot.ASPOT, "f32", raise_on_error=False, want_factors=False, **kw)
-                if probe.status != pot.OK:
-                    # e.g. the proof-form step, whose first move from the cold start can take
-                    # every term of B(z) below the FP64 range of the sums
-                    extra[name] = {"status": pot.status_string(probe.status), "iters": probe.result["iters"]}
-                else:
-                    o2, w2, ev2 = time_solves(pot, d, eps, pot.ASPOT, "f32", 3, 1, None, **kw)
-                    rr = o2[-1].result
-                    extra[name] = {"solves_per_s": 3 / (ev2 / 1e3), "iters": rr["iters"], "cost": rr["cost"],
-                                   "cost_minus_canonical": rr["cost"] - outs[-1].result["cost"]}
-                log(f"{name}: {extra[name]}")
+        log("c4: 512 uneven instances")
+        extra["c4_batched_uneven_512"] = bench_c4(pot, I, dev, eps, 3, args.plain_sample)
+        log(f"c4: {extra['c4_batched_uneven_512']}")
+        log("c2: single 4096^2 instance")
+        extra["c2_single_4096"] = bench_c2(pot, I, dev, eps, args.reps)
+        log("c3: 20000^2 instance, HBM roofline")
+        extra["c3_single_20000"] = bench_c3(pot, I, dev, eps, args.reps)
+        log("registration: 4096 / 2048 points, warm vs cold")
+        extra["registration_4096x2048"] = bench_register(pot, dev, eps)
+        log(f"registration: {extra['registration_4096x2048']}")
         log("shard: rows 0..2499 of the 20000^2 instance (one GPU of 8)")
-        extra["c3_shard_2500x20000"] = bench_shard(pot, I, dev, eps)
+        extra["c3_shard_2500x20000"] = bench_shard(pot, I, dev, eps, args.reps)
         log(f"shard: {extra['c3_shard_2500x20000']}")
-        torch.cuda.empty_cache()
-        # the tuned rule of Algorithm 3 (Theorem 2) on the same instance; its
-        # cost is compared with the ASPOT cost (within eps of the optimum)
-        if args.kind == "f32":
-            for p in (2.0, 3.0):
-                name = f"sinkhorn_tuned_p{int(p)}"
-                o2, w2, ev2 = time_solves(pot, d, eps, pot.SINKHORN, "f32", 3, 1, None, gamma_rule=1, p=p)
-                rr = o2[-1].result
-                extra[name] = {"solves_per_s": 3 / (ev2 / 1e3), "iters": rr["iters"], "cost": rr["cost"],
-                               "gamma": rr["gamma"], "tol": rr["tol"],
-                               "cost_minus_aspot": rr["cost"] - outs[-1].result["cost"] if algo == pot.ASPOT else None}
-                log(f"{name}: {extra[name]}")
-
-    if not args.no_batched:
-        log("batched: 512 uneven instances")
-        extra["batched_uneven_512"] = bench_batched(pot, I, dev, eps, 3, args.plain_sample)
-        log(f"batched: {extra['batched_uneven_512']}")
-        from paper_2601_17196_amd import warmstart as W
-        if os.path.exists(W.WEIGHTS):
-            log("warm start: 1024 instances n = m = 256")
-            extra["warm_batched_1024x256"] = bench_warm(pot, I, dev, eps, 2, args.plain_sample)
-            log(f"warm start: {extra['warm_batched_1024x256']}")
-
     cpu = None
     if not args.no_cpu:
-        log(f"cpu baseline: {args.cpu_iters} oracle iterations")
-        cpu = cpu_baseline(inst, iters, eps, args.cpu_iters)
+        log("cpu baseline: the oracle on a sample of the batch")
+        cpu = cpu_baseline(insts, itc, eps)
         log(f"cpu baseline: {cpu}")
 
     line = {
-        "metric": "POT solves/s at eps=1e-2 (ASPOT, cold start)",
+        "metric": "POT solves/s at eps=1e-2 (ASPOT, learned warm start + batched)",
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 state/exponent + f32 exp" if args.kind != "bf16" else "bf16 cost + f32 exp/f64 sums",
+        "dtype": "f32 cost, f64 state/exponent, f32 exp, f64 sums",
         "data": "synthetic",
-        "config": {"workload": f"single POT instance n=m={n}, 3-D 8 clusters + 10% outliers, "
-                               f"{args.kind} cost, uniform masses 1/1, s=0.9, eps=1e-2, {args.algo} cold",
-                   "n": n, "m": m, "algo": args.algo, "cost": args.kind},
+        "config": {"workload": "1024 POT instances n=m=256, 2-D Gaussian mixtures (2-5 components), Dir(0.5) masses "
+                               "with totals in [0.8,1.2], s=U[0.5,0.9]*min mass, f32 cost, eps=1e-2; learned warm "
+                               "start (BF16 MFMA inference) + one persistent batched ASPOT launch",
+                   "instances": 1024, "n": 256, "m": 256, "algo": "aspot", "cost": "f32"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -176,6 +176,9 @@ typedef struct {
     double* pp;            /* (device) n: p' = r - X'' 1, or NULL */
     double* qq;            /* (device) m: q' = c - X''^T 1, or NULL */
     double* w;             /* (host) ASPOT w at the output point, or NULL */
+    double* moments;       /* (device) 16 doubles, points cost only (d = 2 or 3; missing coordinates 0), or
+                              NULL: M = sum_ij Xbar_ij x_i y_j^T (3 x 3 row-major), sum_i (Xbar 1)_i x_i (3),
+                              sum_j (Xbar^T 1)_j y_j (3), 1^T Xbar 1 (1) of the rounded plan, in FP64 */
 } pot_outputs;
 
 /* Bytes of workspace pot_solve needs for this problem and options (0 on
@@ -293,14 +296,101 @@ size_t pot_warm_workspace_bytes(int32_t batch);
 pot_status pot_warm_predict(int32_t batch, const pot_warm_instance* inst, double eps, const void* weights,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Rigid point-cloud registration through POT (Section 4, "Point Cloud
+ * Registration", and its appendix).  X (n points, fixed) and Y (m points)
+ * in 3-D; the map F(y) = R y + t starts at (R0, t0).  Registration k:
+ *   1. F_k(Y) is formed on the device (FP64 arithmetic, FP32 storage);
+ *   2. POT between X and F_k(Y) with C_ij = cost_scale |x_i - F_k(y_j)|^2
+ *      (the points cost of pot_solve; |C|_max taken on the device), masses
+ *      r, c, mass s, accuracy eps, and gamma_k = max(gamma0 anneal^k,
+ *      gamma_min); with warm = 1 (ASPOT) the solve starts from the previous
+ *      registration's duals with the potentials in cost units kept
+ *      (u, v, w scaled by gamma_{k-1} / gamma_k);
+ *   3. from the rounded plan Xbar, on the device, M = sum_ij Xbar_ij x_i
+ *      F_k(y_j)^T, the barycentre sums and the mass; on the host the centred
+ *      cross-covariance H = M - |Xbar| u_x u_y^T and the rotation dR in SO(3)
+ *      maximising tr(dR^T H) (which minimises sum_ij Xbar_ij
+ *      |x_i - (dR F_k(y_j) + dt)|^2 with dt = u_x - dR u_y), and
+ *      F_{k+1} = (dR R_k, dR t_k + dt);
+ *   4. stop when |cost_k - cost_{k-1}| <= tol cost_{k-1} (cost_k = <C_k,
+ *      Xbar_k>) or after max_steps registrations.
+ * The call synchronises the stream once per registration (the host takes
+ * the 3 x 3 rotation).  The caller owns every buffer; the workspace comes
+ * from pot_register_workspace_bytes.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n, m;          /* points of X and of Y, >= 2 */
+    const float* x;        /* (device) n x 3 row-major, the fixed cloud */
+    const float* y;        /* (device) m x 3 row-major, the moving cloud */
+    const double* r;       /* (device) n masses of X */
+    const double* c;       /* (device) m masses of Y */
+    double s;              /* transported mass, 0 < s <= min(|r|_1, |c|_1) */
+    double cost_scale;     /* > 0: C = cost_scale |x - F(y)|^2 throughout; <= 0: 1 / max_ij |x_i - F0(y_j)|^2 */
+} pot_reg_problem;
+
+typedef struct {
+    double eps;            /* accuracy of every POT solve (Definition 1), > 0 */
+    double gamma0;         /* entropic parameter of the first registration, > 0 */
+    double anneal;         /* factor per registration, in (0, 1] */
+    double gamma_min;      /* floor of gamma_k; <= 0: eps / (4 ln max(n, m)) (Algorithm 2's rule) */
+    double tol;            /* relative change of the transport cost that stops the loop, > 0 */
+    int32_t max_steps;     /* registrations, >= 1 */
+    int32_t warm;          /* 1: warm-start every ASPOT solve from the previous duals; 0: cold */
+    int32_t max_iter;      /* iteration cap of each solve (<= 0: 100000) */
+    int32_t algo;          /* POT_ASPOT or POT_SINKHORN (cold starts) */
+    double R0[9];          /* initial rotation, row-major */
+    double t0[3];          /* initial translation */
+} pot_reg_options;
+
+typedef struct {
+    int32_t status;        /* POT_OK, POT_ERR_NO_CONVERGENCE if a solve hit max_iter, or the error */
+    int32_t steps;         /* registrations run */
+    int32_t total_iters;   /* iterations summed over the solves */
+    int32_t pad;
+    double R[9], t[3];     /* final map */
+    double cost;           /* transport cost of the last registration */
+} pot_reg_result;
+
+/* Per-registration record (every pointer may be NULL; arrays of max_steps
+ * entries): host iters, cost, gamma, E and Rt (12 per registration: R
+ * row-major then t, the map after it); device y_hist (max_steps x m x 3, the
+ * moved cloud each solve saw) and dual_hist (max_steps x (n + m + 1): each
+ * solve's output u, v, w). */
+typedef struct {
+    int32_t* iters;
+    double* cost;
+    double* gamma;
+    double* E;
+    double* Rt;
+    float* y_hist;
+    double* dual_hist;
+} pot_reg_history;
+
+/* Workspace bytes of pot_register (0 on invalid sizes). */
+size_t pot_register_workspace_bytes(const pot_reg_problem* prob);
+
+/* Run the registration loop.  y_out (device, m x 3, may be NULL) receives
+ * F(Y) under the final map.  Returns res->status, or an argument, device or
+ * workspace error (then res->steps tells how many registrations ran). */
+pot_status pot_register(const pot_reg_problem* prob, const pot_reg_options* opts, void* ws, size_t ws_bytes,
+                        pot_reg_result* res, const pot_reg_history* hist, float* y_out, void* stream);
+
+/* Host helper of pot_register: the rotation R in SO(3) (row-major) that
+ * maximises tr(R^T H) for a 3 x 3 matrix H (row-major), i.e. the rotation
+ * of the weighted Procrustes problem with centred cross-covariance
+ * H = sum_ij w_ij x_i y_j^T (R y ~ x).  Computed as the leading eigenvector of
+ * Horn's 4 x 4 quaternion matrix (Jacobi rotations).  No device work. */
+void pot_rigid_align(const double* H, double* R);
+
 /* Measurement hook: set up the problem (as pot_solve does) and run the
  * statistics pass (row sums, column sums and total of B at the start point
  * u0, v0, w0 of opts: the pass every ASPOT and Sinkhorn iteration runs)
- * `reps` times on `stream`.  A pass is two kernels, the tile kernel that
- * streams C (or recomputes it from points) and the finalising kernel; each
- * dispatch is bracketed by HIP events recorded around it.  *avg_ms (host)
- * receives the mean time of the tile kernel, *fin_ms (host, may be NULL) that
- * of the finalising kernel.  Requires prob->cmax > 0 (and cost_scale > 0 for
+ * 3 untimed times and then `reps` times on `stream`.  A pass is two kernels,
+ * the tile kernel that streams C (or recomputes it from points) and the
+ * finalising kernel; each timed dispatch is bracketed by HIP events recorded
+ * around it.  *avg_ms (host) receives the median time of the tile kernel,
+ * *fin_ms (host, may be NULL) that of the finalising kernel.  Requires prob->cmax > 0 (and cost_scale > 0 for
  * points).  Writes only the workspace.  Synchronises the stream. */
 pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
                          int32_t reps, double* avg_ms, double* fin_ms, void* stream);

@@ -168,6 +168,49 @@ __device__ __forceinline__ void unpack_chunk(const f32x4& q, float (&cv)[VW]) {
     }
 }
 
+// Row sums of a sweep step, reduced together.  Each lane holds a partial
+// sum of each of the step's U rows.  A swap of the upper and lower 32 lanes
+// between two rows' registers (v_permlane32_swap) and one add leave row a in
+// lanes 0-31 and row b in lanes 32-63, each lane summing two; a swap of odd
+// and even 16-lane groups between two such results (v_permlane16_swap) leaves
+// one row per 16-lane group, each lane summing four; four DPP steps then add
+// the group.  Every lane of group g ends with the total of one row:
+//   U >= 4: row 4h + ((g & 1) << 1 | g >> 1) in out[h];  U = 2: row g >> 1.
+// The order of the additions is fixed (bitwise reproducible).
+__device__ __forceinline__ double swap32_add(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+__device__ __forceinline__ double swap16_add(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+__device__ __forceinline__ double group16_sum(double v) {
+    v += dpp_d<kQuadX1>(v, 0.0);
+    v += dpp_d<kQuadX2>(v, 0.0);
+    v += dpp_d<kHalfMirror>(v, 0.0);
+    v += dpp_d<kMirror>(v, 0.0);
+    return v;
+}
+
+template <int U>
+__device__ __forceinline__ void rows_reduce(const double (&rs)[U], double (&out)[(U + 3) / 4]) {
+    static_assert(U == 2 || U == 4 || U == 8, "rows per step");
+    if constexpr (U == 2) {
+        const double t = swap32_add(rs[0], rs[1]);
+        out[0] = group16_sum(swap16_add(t, t));
+    } else {
+#pragma unroll
+        for (int h = 0; h < U / 4; ++h)
+            out[h] = group16_sum(swap16_add(swap32_add(rs[4 * h], rs[4 * h + 1]),
+                                            swap32_add(rs[4 * h + 2], rs[4 * h + 3])));
+    }
+}
+
 // One sweep of the member's rows: row sums into S.R (relative to 2^K), column
 // partials into per-thread FP64 accumulators; returns the member's level (the
 // largest row or column sum relative to 2^K).  Wave w takes rows w,
@@ -241,13 +284,18 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
 #pragma unroll
                 for (int e = 0; e < VW; ++e) colacc[k][e] += (double)col32[e];
             }
+            {
+                double tot[(U + 3) / 4];
+                rows_reduce<U>(rsum, tot);
+                const int g = lane >> 4;
+                const int rsel = U == 2 ? (g >> 1) : (((g & 1) << 1) | (g >> 1));
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double t = wave_sum(rsum[u]);
-                const int q = s * U + u;
-                if (q < nq) {
-                    if (lane == 0) S.R[wave + kBWaves * q] = t;
-                    lvl = fmax(lvl, t);
+                for (int h = 0; h < (U + 3) / 4; ++h) {
+                    const int q = s * U + 4 * h + rsel;
+                    if (q < nq) {
+                        if ((lane & 15) == 0) S.R[wave + kBWaves * q] = tot[h];
+                        lvl = fmax(lvl, tot[h]);
+                    }
                 }
             }
 #pragma unroll

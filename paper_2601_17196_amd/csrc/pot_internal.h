@@ -28,6 +28,7 @@ enum Phase : int {
     PH_R2 = 7,       // rounding: FP64 column sums of diag(alpha) X~ -> beta, q'
     PH_R3 = 8,       // rounding: FP64 row sums of X'' and C X'', C q' -> p', cost
     PH_R4 = 9,       // rounding: dense plan
+    PH_R5 = 10,      // plan moments (points cost): z_i = sum_j X~_ij beta_j y_j
 };
 
 // Device control block: every scalar of the algorithm lives here, written
@@ -204,6 +205,12 @@ __host__ __device__ inline BLayout blayout(int n, int m, int G) {
     L.total = L.rowsc + al(8 * (int64_t)kScal * G);
     return L;
 }
+
+// a rigid map F(y) = R y + t (R row-major), passed to kernels by value
+struct RigidMap {
+    double R[9];
+    double t[3];
+};
 
 // one instance of the warm-start inference (pot_warm_predict)
 struct WDesc {

@@ -720,7 +720,7 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
     // no rounding without a finished loop and representable statistics (a
     // uniform test: every workgroup reads the same words)
     if (c.valid != 0 || !c.done || c.status == POT_ERR_NUMERIC) return;
-    if (A.phase == PH_R4 && !c.rounded) return;
+    if ((A.phase == PH_R4 || A.phase == PH_R5) && !c.rounded) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tile = tile_index();
     const int tx = tile % A.nx, ty = tile / A.nx;
@@ -756,6 +756,16 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
             case PH_R4: {
                 double xx = al * w.beta[j] * x;
                 A.plan[(int64_t)i * A.m + j] = c.kappa * xx + c.lambda * w.pp[i] * w.qq[j];
+                break;
+            }
+            case PH_R5: {
+                // z_i = sum_j X~_ij beta_j y_j (the points' coordinates)
+                if constexpr (KIND == POT_COST_SQEUCLID_POINTS) {
+                    const double xb = w.beta[j] * x;
+                    rs += xb * (double)A.y[(int64_t)j * A.d];
+                    rc += xb * (double)A.y[(int64_t)j * A.d + 1];
+                    rq += A.d > 2 ? xb * (double)A.y[(int64_t)j * A.d + 2] : 0.0;
+                }
                 break;
             }
             default: break;
@@ -806,6 +816,10 @@ __global__ __launch_bounds__(kThreads) void round_pass(PassArgs A) {
                 // alpha_i = min(1, r_i / (X~ 1)_i), 0/0 read as 1
                 w.alpha[i] = rs > A.r[i] ? A.r[i] / rs : 1.0;
                 acc[7] += isfinite(rs) ? 0.0 : 1.0;
+            } else if (A.phase == PH_R5) {
+                w.ugrave[i] = rs;      // z_i (dead ASPOT / Sinkhorn state slots after the loop)
+                w.util0[i] = rc;
+                w.util1[i] = rq;
             } else {
                 // p'_i = r_i - (X'' 1)_i
                 double p = A.r[i] - rs;
@@ -1129,6 +1143,65 @@ __global__ __launch_bounds__(1024) void result_kernel(PassArgs A, int algo, pot_
     }
 }
 
+// Moments of the rounded plan Xbar = kappa diag(alpha) X~ diag(beta) + lambda
+// p' q'^T against the points: M = sum_ij Xbar_ij x_i y_j^T = kappa sum_i
+// alpha_i x_i z_i^T + lambda (sum_i p'_i x_i)(sum_j q'_j y_j)^T with z_i of
+// the R5 pass, the barycentre sums sum_i (Xbar 1)_i x_i and sum_j
+// (Xbar^T 1)_j y_j (row and column sums of Xbar from its factors) and the
+// mass: mom[0..8], mom[9..11], mom[12..14], mom[15].
+__global__ __launch_bounds__(1024) void moments_kernel(PassArgs A, double* mom) {
+    __shared__ double s_red[16 * 21];
+    const Ctl& c = *A.ws.ctl;
+    const Ws& w = A.ws;
+    const int tid = threadIdx.x, d = A.d;
+    if (!c.rounded) {
+        if (tid < 16) mom[tid] = NAN;
+        return;
+    }
+    // 0..8 sum alpha_i x_i z_i^T, 9..11 sum p'_i x_i, 12..14 sum (Xbar 1)_i x_i,
+    // 15..17 sum q'_j y_j, 18..20 sum (Xbar^T 1)_j y_j
+    double v[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) v[k] = 0.0;
+    const double lr = c.lambda > 0.0 ? c.lambda * c.nq : 0.0;
+    const double lc = c.lambda > 0.0 ? c.lambda * c.np : 0.0;
+    for (int i = tid; i < A.n; i += blockDim.x) {
+        double xi[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < d; ++a) xi[a] = (double)A.x[(int64_t)i * d + a];
+        const double zi[3] = {w.ugrave[i], w.util0[i], w.util1[i]};
+        const double al = w.alpha[i], p = c.lambda > 0.0 ? w.pp[i] : 0.0;
+        const double row = c.kappa * w.du[i] + lr * p;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) v[3 * a + b] += al * xi[a] * zi[b];
+            v[9 + a] += p * xi[a];
+            v[12 + a] += row * xi[a];
+        }
+    }
+    for (int j = tid; j < A.m; j += blockDim.x) {
+        double yj[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < d; ++a) yj[a] = (double)A.y[(int64_t)j * d + a];
+        const double q = c.lambda > 0.0 ? w.qq[j] : 0.0;
+        const double col = c.kappa * w.dv[j] + lc * q;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[15 + a] += q * yj[a];
+            v[18 + a] += col * yj[a];
+        }
+    }
+    block_sum<21, 16>(v, s_red);
+    if (tid == 0) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) mom[3 * a + b] = c.kappa * v[3 * a + b] + c.lambda * v[9 + a] * v[15 + b];
+        for (int a = 0; a < 3; ++a) {
+            mom[9 + a] = v[12 + a];
+            mom[12 + a] = v[18 + a];
+        }
+        mom[15] = c.mass;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch helpers (C++ linkage, used by pot_api.hip)
 // ---------------------------------------------------------------------------
@@ -1217,6 +1290,11 @@ hipError_t launch_cost_max(int kind, const void* C, int64_t ldc, const float* x,
 hipError_t launch_finish(const PassArgs& A, int algo, double* f, double* g, double* u, double* v, hipStream_t st) {
     int len = A.n > A.m ? A.n : A.m;
     finish_duals<<<(len + 255) / 256, 256, 0, st>>>(A, algo, f, g, u, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const PassArgs& A, double* mom, hipStream_t st) {
+    moments_kernel<<<1, 1024, 0, st>>>(A, mom);
     return hipGetLastError();
 }
 

@@ -1,0 +1,303 @@
+// pot_shared.hip -- many POT instances on one shared cost: feasible Sinkhorn
+// (the loop of Algorithm 3) in the exponential domain, with the kernel of the
+// extended instance K~ = exp(-C~ / gamma) built once in BF16 and the
+// scalings of all instances multiplied by it on the matrix cores.
+//
+// Extended instance of each member b (appendix, "Reduction to Extended OT"):
+// rows r^_b = (r~_b, |c~_b|_1 - s_b), columns c^_b = (c~_b, |r~_b|_1 - s_b),
+// C~ = [[C, 0], [0^T, A]].  One iteration for every member at once:
+//     a_b = r^_b / (K~ b_b)        (GEMM 1: K~ (N x M) times [b_1 .. b_B])
+//     b_b = c^_b / (K~^T a_b)      (GEMM 2: K~^T (M x N) times [a_1 .. a_B])
+// with the row error of iterate t, |a^t (K~ b^t) - r^|_1 (the columns are
+// exact after the b update), taken in the a update of iterate t + 1.
+//
+// Precision: K~ is rounded to BF16 once (it defines the effective cost
+// C' = -gamma ln K~_bf16, which differs from C by at most gamma 2^-8); each
+// scaling enters the products as the sum of two BF16 numbers (hi + lo, about
+// 16 significant bits), so every product K~ b is accumulated in FP32 from an
+// operand accurate to about 2^-17: the iteration converges to the fixed point
+// of the effective cost.  Scalings are FP32.  The kernel is representable
+// only where C / gamma stays inside the FP32 exponent range; the host checks
+// max C / gamma <= 80.
+//
+// Layout: K~ [Np][Mp] and its transpose [Mp][Np], BF16, zero padded to
+// multiples of 64; the scalings [Bp][Np] and [Bp][Mp] (FP32, instance-major);
+// the BF16 operands [2 Bp][Mp] and [2 Bp][Np] (hi row, lo row per member);
+// GEMM outputs [2 Bp][Np] / [2 Bp][Mp] FP32.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "pot_device.h"
+
+namespace pot {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan kept
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+}  // namespace
+
+// K~ and its transpose from the stored cost (FP32 or BF16), cost scale and
+// gamma: K~_ij = exp(-C_ij / gamma) for i < n, j < m; 1 on the dummy row and
+// column; exp(-A / gamma) at the corner; 0 in the padding.
+template <int KIND>
+__global__ void shared_build_kernel(const void* C, int64_t ldc, int n, int m, int Np, int Mp, double inv_gamma,
+                                    double corner, uint16_t* K, uint16_t* KT) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)Np * Mp) return;
+    const int i = (int)(e / Mp), j = (int)(e % Mp);
+    float v = 0.0f;
+    if (i < n && j < m) {
+        double cij;
+        if (KIND == POT_COST_F32) cij = (double)((const float*)C)[(int64_t)i * ldc + j];
+        else cij = (double)bf16_bits_to_f32(((const uint16_t*)C)[(int64_t)i * ldc + j]);
+        v = (float)exp(-cij * inv_gamma);
+    } else if ((i < n && j == m) || (i == n && j < m)) {
+        v = 1.0f;
+    } else if (i == n && j == m) {
+        v = (float)corner;
+    }
+    const uint16_t h = f32_to_bf16_rne(v);
+    K[(int64_t)i * Mp + j] = h;
+    KT[(int64_t)j * Np + i] = h;
+}
+
+// Out[q][i] = sum_k A[i][k] Bop[q][k] for i < rows (multiple of 64), q < cols
+// (multiple of 64), K = depth (multiple of 16): 256 threads, a 64 x 64 tile
+// per workgroup, each wave 16 rows x 64 columns as four 16 x 16 MFMA tiles
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation).  Lane l holds A[row l & 15]
+// [k + 4 (l >> 4) .. +3] and Bop[col l & 15][same k] and receives
+// Out[col l & 15][rows 4 (l >> 4) .. +3].
+__global__ __launch_bounds__(256) void shared_gemm_kernel(const uint16_t* A, const uint16_t* Bop, float* Out,
+                                                          int rows, int cols, int depth) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 64 + wave * 16;
+    const int c0 = blockIdx.y * 64;
+    const int kq = 4 * (lane >> 4);
+    const uint16_t* arow = A + (int64_t)(r0 + (lane & 15)) * depth + kq;
+    const uint16_t* bcol[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) bcol[t] = Bop + (int64_t)(c0 + 16 * t + (lane & 15)) * depth + kq;
+    f32x4v acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < depth; k += 64) {
+        bf16x4 a[4], b[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = *(const bf16x4*)(arow + k + 16 * u);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[u][t] = *(const bf16x4*)(bcol[t] + k + 16 * u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b[u][t], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float* o = Out + (int64_t)(c0 + 16 * t + (lane & 15)) * rows + r0 + kq;
+        *(f32x4v*)o = acc[t];
+    }
+}
+
+// The scaling update of one side for every member: s_new = mass / (sum of
+// the hi and lo products), written to the other parity slot, and its BF16
+// split into the next GEMM's operand.  Row side (err != NULL): the member's
+// row error of the current iterate, |s (K~ b) - r^|_1, partial per block.
+// Members already finished are left alone.
+__global__ __launch_bounds__(256) void shared_update_kernel(const float* prod, const float* mass, const float* scal_cur,
+                                                            float* scal_next, uint16_t* op, int len, int ld,
+                                                            const int32_t* done, double* err_part) {
+    __shared__ double s_red[4];
+    const int b = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (done[b]) return;                    // (uniform over the block)
+    double e = 0.0;
+    if (i < ld) {
+        const float p = prod[(int64_t)(2 * b) * ld + i] + prod[(int64_t)(2 * b + 1) * ld + i];
+        const float ms = mass[(int64_t)b * ld + i];
+        float sn = 0.0f;
+        if (i < len) {
+            if (err_part) e = fabs((double)scal_cur[(int64_t)b * ld + i] * (double)p - (double)ms);
+            sn = ms > 0.0f ? ms / p : 0.0f;
+        }
+        scal_next[(int64_t)b * ld + i] = sn;
+        const uint16_t hi = f32_to_bf16_rne(sn);
+        const uint16_t lo = f32_to_bf16_rne(sn - bf16_bits_to_f32(hi));
+        op[(int64_t)(2 * b) * ld + i] = hi;
+        op[(int64_t)(2 * b + 1) * ld + i] = lo;
+    }
+    if (err_part) {
+        e = wave_sum(e);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0) s_red[wave] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) err_part[(int64_t)b * gridDim.x + blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    }
+}
+
+// Per member: the row error of iterate t (t >= 1) against its threshold;
+// the stop (or max_iter) freezes the member at iterate t.  The last member
+// to finish sets the host flag.
+struct SharedCtl {
+    int32_t* done;         // [B]
+    int32_t* iters;        // [B]
+    int32_t* status;       // [B]
+    int32_t* out_par;      // [B] parity slot of the output scalings
+    double* E;             // [B]
+    const double* tol;     // [B]
+    int32_t* ndone;        // [1]
+    int32_t* host_done;    // pinned host flag, or NULL
+};
+
+__global__ void shared_decide_kernel(SharedCtl S, const double* err_part, int nblk, int B, int t, int max_iter) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || S.done[b]) return;
+    double e = 0.0;
+    for (int k = 0; k < nblk; ++k) e += err_part[(int64_t)b * nblk + k];
+    bool stop = false;
+    if (t >= 1) {
+        S.E[b] = e;
+        stop = e <= S.tol[b];
+    }
+    if (!(e == e) || (t >= 1 && !isfinite(e))) {
+        S.done[b] = 1;
+        S.status[b] = POT_ERR_NUMERIC;
+        S.iters[b] = t;
+        S.out_par[b] = t & 1;
+    } else if (stop || t >= max_iter) {
+        S.done[b] = 1;
+        S.status[b] = stop ? POT_OK : POT_ERR_NO_CONVERGENCE;
+        S.iters[b] = t;
+        S.out_par[b] = t & 1;
+    } else {
+        return;
+    }
+    const int k = atomicAdd(S.ndone, 1);
+    if (k + 1 == B && S.host_done) __hip_atomic_store(S.host_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Member b's setup results into the batch arrays: r^ and c^ (FP32) and its
+// threshold.  (ws: the single-instance workspace the setup kernel filled.)
+__global__ void shared_gather_kernel(Ws w, int n, int m, int Np, int Mp, int b, float* rhat, float* chat,
+                                     double* tol) {
+    const Ctl& c = *w.ctl;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < Np) rhat[(int64_t)b * Np + k] = k < n ? (float)w.rt[k] : (k == n ? (float)c.rhat_d : 0.0f);
+    if (k < Mp) chat[(int64_t)b * Mp + k] = k < m ? (float)w.ct[k] : (k == m ? (float)c.chat_d : 0.0f);
+    if (k == 0) tol[b] = c.tol;
+}
+
+// Start of the loop: b = 1 on every real and dummy column (log b = 0, the
+// cold start of Algorithm 3), its BF16 operand, the member flags.
+__global__ void shared_init_kernel(float* bsc, uint16_t* bop, int m, int Mp, int B, SharedCtl S) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (k < Mp) {
+        const float v = k <= m ? 1.0f : 0.0f;
+        bsc[(int64_t)b * Mp + k] = v;
+        bop[(int64_t)(2 * b) * Mp + k] = f32_to_bf16_rne(v);
+        bop[(int64_t)(2 * b + 1) * Mp + k] = 0;
+    }
+    if (k == 0) {
+        S.done[b] = 0;
+        S.iters[b] = 0;
+        S.status[b] = POT_OK;
+        S.out_par[b] = 0;
+        S.E[b] = INFINITY;
+        if (b == 0) *S.ndone = 0;
+    }
+}
+
+// Member b's output scalings as log-scalings of X~_ij = exp(f_i + g_j -
+// C_ij / gamma) into the rounding slots of the single-instance workspace
+// (ubar, vbar; the dummy entries into the control block), its finish state,
+// and the caller's optional f, g.  abuf: [2][Bp][Np] by parity.
+__global__ void shared_load_duals_kernel(Ws w, const float* abuf, const float* bsc, int n, int m, int Np, int Mp,
+                                         int Bp, int b, SharedCtl S, double* fo, double* go) {
+    Ctl& c = *w.ctl;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const float* a = abuf + ((int64_t)S.out_par[b] * Bp + b) * Np;
+    if (k < n) {
+        const double f = log((double)a[k]);
+        w.ubar[k] = f;
+        if (fo) fo[k] = f;
+    }
+    if (k < m) {
+        const double g = log((double)bsc[(int64_t)b * Mp + k]);
+        w.vbar[k] = g;
+        if (go) go[k] = g;
+    }
+    if (k == 0) {
+        c.done = 1;
+        c.status = S.status[b];
+        c.iters = S.iters[b];
+        c.E = S.E[b];
+        c.out_par = 0;
+        c.ad[0] = c.ad[1] = log((double)a[n]);
+        c.bd = log((double)bsc[(int64_t)b * Mp + m]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+hipError_t launch_shared_build(int kind, const void* C, int64_t ldc, int n, int m, int Np, int Mp, double inv_gamma,
+                               double corner, uint16_t* K, uint16_t* KT, hipStream_t st) {
+    const int64_t tot = (int64_t)Np * Mp;
+    const int blocks = (int)((tot + 255) / 256);
+    if (kind == POT_COST_BF16)
+        shared_build_kernel<POT_COST_BF16><<<blocks, 256, 0, st>>>(C, ldc, n, m, Np, Mp, inv_gamma, corner, K, KT);
+    else
+        shared_build_kernel<POT_COST_F32><<<blocks, 256, 0, st>>>(C, ldc, n, m, Np, Mp, inv_gamma, corner, K, KT);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_gemm(const uint16_t* A, const uint16_t* Bop, float* Out, int rows, int cols, int depth,
+                              hipStream_t st) {
+    shared_gemm_kernel<<<dim3(rows / 64, cols / 64), 256, 0, st>>>(A, Bop, Out, rows, cols, depth);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_update(const float* prod, const float* mass, const float* cur, float* next, uint16_t* op,
+                                int len, int ld, int B, const int32_t* done, double* err_part, hipStream_t st) {
+    shared_update_kernel<<<dim3((ld + 255) / 256, B), 256, 0, st>>>(prod, mass, cur, next, op, len, ld, done, err_part);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_gather(const Ws& w, int n, int m, int Np, int Mp, int b, float* rhat, float* chat, double* tol,
+                                hipStream_t st) {
+    const int len = Np > Mp ? Np : Mp;
+    shared_gather_kernel<<<(len + 255) / 256, 256, 0, st>>>(w, n, m, Np, Mp, b, rhat, chat, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_init(float* bsc, uint16_t* bop, int m, int Mp, int B, const SharedCtl& S, hipStream_t st) {
+    shared_init_kernel<<<dim3((Mp + 255) / 256, B), 256, 0, st>>>(bsc, bop, m, Mp, B, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_load_duals(const Ws& w, const float* abuf, const float* bsc, int n, int m, int Np, int Mp,
+                                    int Bp, int b, const SharedCtl& S, double* fo, double* go, hipStream_t st) {
+    const int len = n > m ? n : m;
+    shared_load_duals_kernel<<<(len + 255) / 256, 256, 0, st>>>(w, abuf, bsc, n, m, Np, Mp, Bp, b, S, fo, go);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_decide(const SharedCtl& S, const double* err_part, int nblk, int B, int t, int max_iter,
+                                hipStream_t st) {
+    shared_decide_kernel<<<(B + 63) / 64, 64, 0, st>>>(S, err_part, nblk, B, t, max_iter);
+    return hipGetLastError();
+}
+
+}  // namespace pot

@@ -17,7 +17,7 @@ __all__ = [
     "load", "lib_path", "ASPOT", "SINKHORN", "COST_F32", "COST_BF16", "COST_POINTS",
     "FLAG_WANT_PLAN", "FLAG_NO_ROUND", "Problem", "Options", "Result", "Outputs",
     "solve", "solve_batched", "workspace_bytes", "status_string", "last_error", "SolveOutput",
-    "PotError", "time_pass", "result_from_device", "FLAG_ASYNC",
+    "PotError", "time_pass", "result_from_device", "FLAG_ASYNC", "register", "rigid_align",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -85,7 +85,30 @@ class Result(ct.Structure):
 class Outputs(ct.Structure):
     _fields_ = [("plan", ct.c_void_p), ("f", ct.c_void_p), ("g", ct.c_void_p), ("u", ct.c_void_p),
                 ("v", ct.c_void_p), ("alpha", ct.c_void_p), ("beta", ct.c_void_p),
-                ("pp", ct.c_void_p), ("qq", ct.c_void_p), ("w", ct.POINTER(ct.c_double))]
+                ("pp", ct.c_void_p), ("qq", ct.c_void_p), ("w", ct.POINTER(ct.c_double)),
+                ("moments", ct.c_void_p)]
+
+
+class RegProblem(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("m", ct.c_int32), ("x", ct.c_void_p), ("y", ct.c_void_p),
+                ("r", ct.c_void_p), ("c", ct.c_void_p), ("s", ct.c_double), ("cost_scale", ct.c_double)]
+
+
+class RegOptions(ct.Structure):
+    _fields_ = [("eps", ct.c_double), ("gamma0", ct.c_double), ("anneal", ct.c_double),
+                ("gamma_min", ct.c_double), ("tol", ct.c_double), ("max_steps", ct.c_int32),
+                ("warm", ct.c_int32), ("max_iter", ct.c_int32), ("algo", ct.c_int32),
+                ("R0", ct.c_double * 9), ("t0", ct.c_double * 3)]
+
+
+class RegResult(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("steps", ct.c_int32), ("total_iters", ct.c_int32), ("pad", ct.c_int32),
+                ("R", ct.c_double * 9), ("t", ct.c_double * 3), ("cost", ct.c_double)]
+
+
+class RegHistory(ct.Structure):
+    _fields_ = [("iters", ct.c_void_p), ("cost", ct.c_void_p), ("gamma", ct.c_void_p), ("E", ct.c_void_p),
+                ("Rt", ct.c_void_p), ("y_hist", ct.c_void_p), ("dual_hist", ct.c_void_p)]
 
 
 _lib = None
@@ -123,6 +146,13 @@ def load():
     lib.pot_solve_noalloc.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.POINTER(Result),
                                       ct.POINTER(Outputs), ct.c_void_p]
     lib.pot_solve_noalloc.restype = ct.c_int
+    lib.pot_register_workspace_bytes.argtypes = [ct.POINTER(RegProblem)]
+    lib.pot_register_workspace_bytes.restype = ct.c_size_t
+    lib.pot_register.argtypes = [ct.POINTER(RegProblem), ct.POINTER(RegOptions), ct.c_void_p, ct.c_size_t,
+                                 ct.POINTER(RegResult), ct.POINTER(RegHistory), ct.c_void_p, ct.c_void_p]
+    lib.pot_register.restype = ct.c_int
+    lib.pot_rigid_align.argtypes = [ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
+    lib.pot_rigid_align.restype = None
     lib.pot_time_pass.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.c_void_p, ct.c_size_t,
                                   ct.c_int32, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.c_void_p]
     lib.pot_time_pass.restype = ct.c_int
@@ -307,6 +337,83 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     return so
 
 
+def rigid_align(H):
+    """The rotation in SO(3) maximising tr(R^T H) (pot_rigid_align, host)."""
+    Hc = (ct.c_double * 9)(*[float(v) for v in np.asarray(H, dtype=np.float64).ravel()])
+    Rc = (ct.c_double * 9)()
+    load().pot_rigid_align(Hc, Rc)
+    return np.array(list(Rc)).reshape(3, 3)
+
+
+@dataclasses.dataclass
+class RegisterOutput:
+    status: int
+    R: np.ndarray
+    t: np.ndarray
+    steps: int
+    total_iters: int
+    cost: float
+    iters: np.ndarray
+    costs: np.ndarray
+    gammas: np.ndarray
+    E: np.ndarray
+    Rt: np.ndarray
+    y_out: object = None
+    y_hist: object = None
+    dual_hist: object = None
+
+
+def register(x, y, r, c, s, eps=1e-2, gamma0=4.4e-3, anneal=0.83, gamma_min=0.0, tol=1e-5, max_steps=60,
+             warm=True, max_iter=0, algo=ASPOT, cost_scale=0.0, R0=None, t0=None, history=False, stream=None,
+             raise_on_error=True):
+    """Rigid registration of the cloud y (m x 3) onto x (n x 3) through POT
+    (pot_register).  Tensors on the GPU: x, y float32, r, c float64."""
+    import torch
+    lib = load()
+    dev = x.device
+    n, m = int(x.shape[0]), int(y.shape[0])
+    prob = RegProblem()
+    prob.n, prob.m = n, m
+    prob.x, prob.y, prob.r, prob.c = _ptr(x), _ptr(y), _ptr(r), _ptr(c)
+    prob.s = float(s)
+    prob.cost_scale = float(cost_scale)
+    o = RegOptions()
+    o.eps, o.gamma0, o.anneal, o.gamma_min, o.tol = float(eps), float(gamma0), float(anneal), float(gamma_min), float(tol)
+    o.max_steps, o.warm, o.max_iter, o.algo = int(max_steps), int(bool(warm)), int(max_iter), int(algo)
+    R0 = np.eye(3) if R0 is None else np.asarray(R0, dtype=np.float64)
+    t0 = np.zeros(3) if t0 is None else np.asarray(t0, dtype=np.float64)
+    for k in range(9):
+        o.R0[k] = float(R0.ravel()[k])
+    for k in range(3):
+        o.t0[k] = float(t0[k])
+    nbytes = int(lib.pot_register_workspace_bytes(ct.byref(prob)))
+    if nbytes == 0:
+        raise PotError(ERR_INVALID_ARG, "invalid sizes")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    aligned = (ws.data_ptr() + 255) & ~255
+    iters = np.zeros(max_steps, dtype=np.int32)
+    costs, gammas, Es = np.zeros(max_steps), np.zeros(max_steps), np.zeros(max_steps)
+    Rt = np.zeros((max_steps, 12))
+    h = RegHistory()
+    h.iters, h.cost, h.gamma, h.E, h.Rt = (a.ctypes.data for a in (iters, costs, gammas, Es, Rt))
+    yh = dh = None
+    if history:
+        yh = torch.zeros((max_steps, m, 3), dtype=torch.float32, device=dev)
+        dh = torch.zeros((max_steps, n + m + 1), dtype=torch.float64, device=dev)
+        h.y_hist, h.dual_hist = yh.data_ptr(), dh.data_ptr()
+    y_out = torch.empty((m, 3), dtype=torch.float32, device=dev)
+    res = RegResult()
+    st = lib.pot_register(ct.byref(prob), ct.byref(o), ct.c_void_p(aligned), ct.c_size_t(nbytes), ct.byref(res),
+                          ct.byref(h), ct.c_void_p(y_out.data_ptr()), _stream_ptr(stream))
+    if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
+        raise PotError(st, last_error())
+    k = int(res.steps)
+    return RegisterOutput(status=int(st), R=np.array(list(res.R)).reshape(3, 3), t=np.array(list(res.t)), steps=k,
+                          total_iters=int(res.total_iters), cost=float(res.cost), iters=iters[:k], costs=costs[:k],
+                          gammas=gammas[:k], E=Es[:k], Rt=Rt[:k], y_out=y_out,
+                          y_hist=None if yh is None else yh[:k], dual_hist=None if dh is None else dh[:k])
+
+
 def batch_problems(problems):
     """ctypes array of Problem for a list of dicts with keys r, c, s, C (device
     tensors; optional ldc, kind, cmax)."""
@@ -466,9 +573,9 @@ def to_device_instance(inst, device="cuda", kind="f32", pad_ldc=False):
 
 def time_pass(r, c, s, eps, reps=50, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=0.0,
               cmax=1.0, u0=None, v0=None, w0=0.0, stream=None, tile_rows=0):
-    """Mean kernel times (ms) of the statistics pass at (u0, v0, w0), from
-    HIP events recorded around each dispatch (pot_time_pass): returns
-    (tile kernel, finalising kernel)."""
+    """Median kernel times (ms) of the statistics pass at (u0, v0, w0) over
+    `reps` launches after 3 untimed ones, from HIP events recorded around each
+    dispatch (pot_time_pass): returns (tile kernel, finalising kernel)."""
     import torch
     lib = load()
     prob = make_problem(r, c, s, C=C, x=x, y=y, kind=kind, ldc=ldc, cost_scale=cost_scale, cmax=cmax)

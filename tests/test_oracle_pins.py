@@ -739,3 +739,72 @@ def test_plan_eval_matches_dense_rounding(oracle, seed):
     assert abs(pe["cost"] - float(np.sum(Cb * X))) <= 1e-14
     pe2 = oracle.plan_eval(C, gamma, f, gg, rd["alpha"], rd["beta"], rd["kappa"], rd["lam"], rd["pp"], rd["qq"])
     assert abs(pe2["cost"] - rd["cost"]) <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Registration (Section 4 and the appendix's POT formulation): the weighted
+# Procrustes step recovers a known rigid map exactly from a matching plan,
+# returns a proper rotation even where the unconstrained optimum is a
+# reflection, and no other rotation does better on the stated objective.
+# ---------------------------------------------------------------------------
+def _rot(axis, ang):
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * K @ K
+
+
+def _objective(X, Y, P, R, t):
+    from oracle import register as G
+    return float(np.sum(P * G.sqeuclid(X, G.apply(R, t, Y))))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_procrustes_recovers_a_known_map(seed):
+    from oracle import register as G
+    g = np.random.default_rng(seed)
+    Y = g.normal(size=(40, 3))
+    R0 = _rot(g.normal(size=3), g.uniform(0.1, 3.0))
+    t0 = g.normal(size=3)
+    X = G.apply(R0, t0, Y)
+    P = np.diag(g.uniform(0.5, 1.5, 40))          # point i matched to point i, uneven weights
+    R, t = G.procrustes(X, Y, P)
+    assert np.max(np.abs(R - R0)) <= 1e-12 and np.max(np.abs(t - t0)) <= 1e-12
+
+
+def test_procrustes_proper_rotation_and_optimal():
+    from oracle import register as G
+    g = np.random.default_rng(7)
+    Y = g.normal(size=(30, 3))
+    X = Y * np.array([1.0, 1.0, -1.0])             # a mirror image: the best orthogonal map is a reflection
+    P = g.uniform(0.0, 1.0, (30, 30)) * 0.01 + np.eye(30)
+    R, t = G.procrustes(X, Y, P)
+    assert abs(np.linalg.det(R) - 1.0) <= 1e-12 and np.max(np.abs(R @ R.T - np.eye(3))) <= 1e-12
+    best = _objective(X, Y, P, R, t)
+    for k in range(200):                           # random proper rotations with their best translations
+        Rr = _rot(g.normal(size=3), g.uniform(0, np.pi))
+        ux, uy, _, _ = G.plan_moments(X, Y, P)
+        assert best <= _objective(X, Y, P, Rr, ux - Rr @ uy) + 1e-12
+    # the increment composed onto a pose is the pose that aligns the original cloud
+    R1, t1 = _rot([1, 2, 3], 0.4), np.array([0.1, -0.2, 0.3])
+    dR, dt = G.procrustes(X, G.apply(R1, t1, Y), P)
+    Rd, td = G.procrustes(X, Y, P)
+    assert np.max(np.abs(dR @ R1 - Rd)) <= 1e-10 and np.max(np.abs(dR @ t1 + dt - td)) <= 1e-10
+
+
+def test_registration_loop_aligns_a_partial_copy(oracle):
+    """A cloud and a misaligned copy of half of it: the loop recovers the
+    map (the copy's points land on their originals) and the transport cost
+    falls to about the entropic floor."""
+    from oracle import register as G
+    g = np.random.default_rng(11)
+    X = g.normal(0.0, 0.3, size=(60, 3)) + g.choice([-0.6, 0.6], size=(60, 1)) * np.array([1.0, 0.0, 0.0])
+    R0, t0 = _rot([0.3, 1.0, 0.2], 0.35), np.array([0.15, -0.1, 0.05])
+    Y = G.apply(R0.T, -R0.T @ t0, X[:30]).astype(np.float32).astype(np.float64)   # X[:30] = R0 y + t0
+    r = np.full(60, 1.0 / 60)
+    c = np.full(30, 1.0 / 30)
+    s = 0.4 * 30 / 60
+    R, t, steps = G.register(X, Y, r, c, s, max_steps=40)
+    err = np.max(np.abs(G.apply(R, t, Y) - X[:30]))
+    assert err <= 0.02, err
+    assert steps[-1].cost <= 0.05 * steps[0].cost
