@@ -61,7 +61,7 @@ def measured_traffic(name):
         return None
     from paper_2601_17196_amd import profile_summary as PS
     s = json.load(open(path))
-    if s.get("kernel_source_hash") != PS.kernel_source_hash():
+    if s.get("kernel_source_hash") != PS.kernel_source_hash(s.get("kernel_sources")):
         return None
     return s.get("traffic_bytes")
 
@@ -159,14 +159,16 @@ def headline(pot, I, dev, eps, steps, warmup, plain_sample, cold_reps):
         if k > 0:
             tc.append(t)
     resc = out[1]
-    sample = list(range(0, len(insts), len(insts) // plain_sample))[:plain_sample]
-    pot.solve(probs[0]["r"], probs[0]["c"], probs[0]["s"], eps, C=probs[0]["C"], cmax=1.0, want_factors=False)
+    sample = list(range(0, len(insts), max(1, len(insts) // max(plain_sample, 1))))[:plain_sample]
+    tp = None
+    if sample:
+        pot.solve(probs[0]["r"], probs[0]["c"], probs[0]["s"], eps, C=probs[0]["C"], cmax=1.0, want_factors=False)
 
-    def plain():
-        for j in sample:
-            pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0,
-                      want_factors=False)
-    tp, _ = _event_ms(plain)
+        def plain():
+            for j in sample:
+                pot.solve(probs[j]["r"], probs[j]["c"], probs[j]["s"], eps, C=probs[j]["C"], cmax=1.0,
+                          want_factors=False)
+        tp, _ = _event_ms(plain)
     itw = np.array([r["iters"] for r in resw])
     itc = np.array([r["iters"] for r in resc])
     elems = _work_elems(insts, resw)
@@ -179,7 +181,7 @@ def headline(pot, I, dev, eps, steps, warmup, plain_sample, cold_reps):
         "instances": len(insts),
         "warm_batched_solves_per_s": len(insts) * steps / (ms / 1e3),
         "cold_batched_solves_per_s": len(insts) / (_median(tc) / 1e3),
-        "plain_solves_per_s": len(sample) / (tp / 1e3), "plain_sample": len(sample),
+        "plain_solves_per_s": len(sample) / (tp / 1e3) if tp else None, "plain_sample": len(sample),
         "batched_launch_ms_median": med_b, "inference_ms_median": _median(t_inf),
         "cold_batched_launch_ms_median": _median(tc),
         "warm_kept": int(sum(r["used_warm"] for r in resw)),
@@ -430,6 +432,96 @@ def bench_register(pot, dev, eps, n=4096):
     return out
 
 
+def bench_tracking(pot, I, dev, eps, count=1024, reps=3):
+    """Warm starts from a previous solve on the C5 batch shape: every
+    instance's clouds move by a small rigid step (target rotated by 1 degree
+    about its centroid and shifted by 0.005, as in one step of tracking or
+    registration), and the moved batch is solved batched from the previous
+    solution's duals (warm, with the phi check) and from zero (cold)."""
+    import numpy as np
+    import torch
+    insts = I.c5_batch(count)
+    probs = _batch_probs(pot, insts, dev)
+    ws = torch.empty(pot.workspace_bytes_batched(probs) + 512, dtype=torch.uint8, device=dev)
+    st0, res0, duals = pot.solve_batched(probs, eps, workspace=ws, want_uv=True)
+    th = np.deg2rad(1.0)
+    Rz = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    moved = []
+    for i in insts:
+        y = i.y.astype(np.float64)
+        mu = y.mean(0)
+        y2 = ((y - mu) @ Rz.T + mu + 0.005).astype(np.float32)
+        x = i.x.astype(np.float64)
+        D = ((x[:, None, :] - y2.astype(np.float64)[None, :, :]) ** 2).sum(-1) * i.cost_scale
+        moved.append(np.ascontiguousarray(D.astype(np.float32)))
+    probs2 = []
+    for p, C in zip(probs, moved):
+        q = dict(p)
+        q["C"] = torch.from_numpy(C).to(dev)
+        q["ldc"] = C.shape[1]
+        q["cmax"] = 0.0
+        probs2.append(q)
+    u0 = [d[2] for d in duals]
+    v0 = [d[3] for d in duals]
+    w0 = [r["w"] for r in res0]
+    run_w = lambda: pot.solve_batched(probs2, eps, u0=u0, v0=v0, w0=w0, warm_check=True, workspace=ws,
+                                      want_duals=False)
+    run_c = lambda: pot.solve_batched(probs2, eps, workspace=ws, want_duals=False)
+    out = {}
+    for name, fn in (("warm", run_w), ("cold", run_c)):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t, (st, res, _) = _event_ms(fn)
+            ts.append(t)
+        its = np.array([r["iters"] for r in res])
+        out[name] = {"solves_per_s": count / (_median(ts) / 1e3), "ms_median": _median(ts),
+                     "iters_total": int(its.sum()), "iters_median": float(np.median(its)), "iters_max": int(its.max()),
+                     "all_ok": st == 0, "warm_kept": int(sum(r["used_warm"] for r in res))}
+    out["speedup_warm_over_cold"] = out["warm"]["solves_per_s"] / out["cold"]["solves_per_s"]
+    del ws, probs, probs2
+    torch.cuda.empty_cache()
+    return out
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def bench_shared(pot, dev, eps, n=1024, B=256):
+    """Shared-cost batch (pot_solve_shared): B members with their own
+    Dirichlet marginals and s on one n x n cost (2-D uniform points), gamma =
+    max C / 60; members/s, and the matrix-core product's roofline (2 x rows x
+    depth x 2 batch flops per launch against the dense BF16 peak)."""
+    import numpy as np
+    import torch
+    from paper_2601_17196_amd import instances as I
+    inst = I.uniform_pair(n, n, 2, 77)
+    C = torch.from_numpy(inst.C32).to(dev)
+    cmax = float(inst.C32.max())
+    gamma = cmax / 60.0
+    g = np.random.default_rng(5)
+    mem = []
+    for _ in range(B):
+        r = g.dirichlet(np.ones(n)) * g.uniform(0.8, 1.2)
+        c = g.dirichlet(np.ones(n)) * g.uniform(0.8, 1.2)
+        mem.append(dict(r=torch.from_numpy(r).to(dev), c=torch.from_numpy(c).to(dev),
+                        s=float(g.uniform(0.5, 0.9) * min(r.sum(), c.sum()))))
+    ws = torch.empty(pot.workspace_bytes_shared(C, B) + 512, dtype=torch.uint8, device=dev)
+    pot.solve_shared(C, mem, eps, gamma, cmax=cmax, workspace=ws, want_duals=False)        # warm-up
+    ms, (st, res, _) = _event_ms(lambda: pot.solve_shared(C, mem, eps, gamma, cmax=cmax, workspace=ws,
+                                                          want_duals=False))
+    its = [r["iters"] for r in res]
+    gms, (rows, cols, depth) = pot.time_shared_gemm(C, B, gamma, cmax, reps=20)
+    flops = 2.0 * rows * cols * depth
+    ach = flops / (gms * 1e-3) / 1e12
+    return {"n": n, "members": B, "gamma": gamma, "status": st, "members_per_s": B / (ms / 1e3), "ms": ms,
+            "iters_max": int(max(its)), "iters_median": float(np.median(its)), "gemm_us": gms * 1e3,
+            "gemm_shape": [rows, cols, depth],
+            "roofline": {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None},
+            "gemm_hbm_GB_per_s": (rows * depth * 2 + cols * depth * 2 + cols * rows * 4) / (gms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -465,7 +557,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
         if args.pmc_probe == "c5":
-            headline(pot, I, dev, eps, 1, 0, 1, 0)
+            headline(pot, I, dev, eps, 1, 0, 0, 1)
         elif args.pmc_probe == "c2":
             inst = I.c2(0, n=4096)
             d = pot.to_device_instance(inst, dev, kind="f32")
@@ -492,6 +584,9 @@ def main():
     log(f"batched kernel roofline: {roof}")
     extra = {"c5_warm_cold_plain": info}
     if not args.no_extra:
+        log("tracking: the C5 batch moved by a small rigid step, warm from the previous solve vs cold")
+        extra["c5_tracking_warm_batched"] = bench_tracking(pot, I, dev, eps)
+        log(f"tracking: {extra['c5_tracking_warm_batched']}")
         log("c4: 512 uneven instances")
         extra["c4_batched_uneven_512"] = bench_c4(pot, I, dev, eps, 3, args.plain_sample)
         log(f"c4: {extra['c4_batched_uneven_512']}")
@@ -502,6 +597,9 @@ def main():
         log("registration: 4096 / 2048 points, warm vs cold")
         extra["registration_4096x2048"] = bench_register(pot, dev, eps)
         log(f"registration: {extra['registration_4096x2048']}")
+        log("shared cost: 256 members on one 1024^2 cost")
+        extra["shared_cost_1024_x256"] = bench_shared(pot, dev, eps)
+        log(f"shared: {extra['shared_cost_1024_x256']}")
         log("shard: rows 0..2499 of the 20000^2 instance (one GPU of 8)")
         extra["c3_shard_2500x20000"] = bench_shard(pot, I, dev, eps, args.reps)
         log(f"shard: {extra['c3_shard_2500x20000']}")

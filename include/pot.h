@@ -297,6 +297,59 @@ pot_status pot_warm_predict(int32_t batch, const pot_warm_instance* inst, double
                             void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Many POT instances on one shared cost (members b = 1..batch with their own
+ * r_b, c_b, s_b): feasible Sinkhorn, the loop of Algorithm 3, in the
+ * exponential domain as printed there, a_b = r^_b / (K~ b_b),
+ * b_b = c^_b / (K~^T a_b), with the kernel of the extended instance
+ * K~ = exp(-C~ / gamma) built once and every member's scalings multiplied by
+ * it at once on the matrix cores (BF16 K~, each scaling as a sum of two BF16
+ * numbers, FP32 accumulation).  The extended instance, the smoothing, the
+ * stopping rule and the rounding onto U(r_b, c_b, s_b) are those of
+ * pot_solve with algo POT_SINKHORN, per member; gamma is shared and must be
+ * given.  K~ is representable only if max C / gamma <= 80 (larger ratios
+ * return POT_ERR_UNSUPPORTED: use pot_solve_batched, which works in the log
+ * domain).  Rounding K~ to BF16 changes the effective cost by at most
+ * gamma 2^-8 per entry.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t n, m;          /* cost size, >= 1 */
+    int32_t kind;          /* POT_COST_F32 or POT_COST_BF16 */
+    int32_t pad;
+    const void* C;         /* (device) n x m row-major, leading dimension ldc */
+    int64_t ldc;
+    double cmax;           /* max_ij C_ij; <= 0: computed on the device */
+} pot_shared_cost;
+
+typedef struct {
+    const double* r;       /* (device) n masses */
+    const double* c;       /* (device) m masses */
+    double s;              /* transported mass */
+    double* f;             /* (device) n: output log-scalings, X~_ij = exp(f_i + g_j - C_ij / gamma), or NULL */
+    double* g;             /* (device) m, or NULL */
+} pot_shared_member;
+
+/* Workspace bytes of pot_solve_shared (0 on invalid sizes). */
+size_t pot_workspace_bytes_shared(const pot_shared_cost* cost, int32_t batch);
+
+/* Solve `batch` members on the shared cost.  opts: algo POT_SINKHORN,
+ * gamma > 0 (shared), eps, tol (<= 0: each member's eps~), A, max_iter
+ * (<= 0: 100000), flags (POT_FLAG_NO_ROUND); other fields ignored.  members
+ * and res are host arrays of `batch`.  Polls a pinned host flag every
+ * check_every iterations; synchronises the stream before returning.
+ * Returns POT_OK if every member is OK, else the first failing status. */
+pot_status pot_solve_shared(const pot_shared_cost* cost, int32_t batch, const pot_shared_member* members,
+                            const pot_options* opts, void* ws, size_t ws_bytes, pot_result* res, void* stream);
+
+/* Measurement hook: build K~ for the shared cost (cmax and gamma given) and
+ * time the first product of an iteration, K~ times every member's split
+ * scalings (rows x 2 batch x columns, padded to multiples of 64 and 32
+ * members), 3 untimed and then `reps` times with HIP events around each
+ * launch; *med_ms receives the median.  Writes only the workspace
+ * (pot_workspace_bytes_shared).  Synchronises the stream. */
+pot_status pot_time_shared_gemm(const pot_shared_cost* cost, int32_t batch, double gamma, void* ws, size_t ws_bytes,
+                                int32_t reps, double* med_ms, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Rigid point-cloud registration through POT (Section 4, "Point Cloud
  * Registration", and its appendix).  X (n points, fixed) and Y (m points)
  * in 3-D; the map F(y) = R y + t starts at (R0, t0).  Registration k:

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpot.so")
-SOURCES = ["pot_kernels.hip", "pot_batched.hip", "pot_warm.hip", "pot_register.hip", "pot_api.hip"]
+SOURCES = ["pot_kernels.hip", "pot_batched.hip", "pot_warm.hip", "pot_register.hip", "pot_shared.hip", "pot_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -707,6 +707,230 @@ static pot_status register_rigid(const pot_reg_problem* p, const pot_reg_options
     return (pot_status)res->status;
 }
 
+// ---------------------------------------------------------------------------
+// shared-cost batches: exponential-domain feasible Sinkhorn for many members
+// on one cost, products on the matrix cores (pot_shared.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_shared_build(int kind, const void* C, int64_t ldc, int n, int m, int Np, int Mp, double inv_gamma,
+                               double corner, uint16_t* K, uint16_t* KT, hipStream_t st);
+hipError_t launch_shared_gemm(const uint16_t* A, const uint16_t* Bop, float* Out, int rows, int cols, int depth,
+                              const int32_t* ndone, int B, hipStream_t st);
+hipError_t launch_shared_update(const float* prod, const float* mass, const float* cur, float* next, uint16_t* op,
+                                int len, int ld, int B, const int32_t* done, double* err_part, hipStream_t st);
+hipError_t launch_shared_decide(const SharedCtl& S, const double* err_part, int nblk, int B, int t, int max_iter,
+                                hipStream_t st);
+hipError_t launch_shared_gather(const Ws& w, int n, int m, int Np, int Mp, int b, int B, float* rhat, float* chat,
+                                double* tol, const SharedCtl& S, hipStream_t st);
+hipError_t launch_shared_init(float* bsc, uint16_t* bop, int m, int Mp, int B, const SharedCtl& S, hipStream_t st);
+hipError_t launch_shared_load_duals(const Ws& w, const float* abuf, const float* bsc, int n, int m, int Np, int Mp,
+                                    int Bp, int b, const SharedCtl& S, double* fo, double* go, hipStream_t st);
+
+static int round_up(int x, int k) { return (x + k - 1) / k * k; }
+
+// workspace of a shared-cost batch
+struct SharedLayout {
+    int Np, Mp, Bp, nblk;
+    size_t solve, K, KT, abuf, bsc, aop, bop, P, Q, rhat, chat, errp, done, iters, status, outpar, E, tol, ndone,
+        res, total;
+};
+
+static SharedLayout shared_layout(const pot_shared_cost* cost, int batch) {
+    SharedLayout L;
+    L.Np = round_up(cost->n + 1, 64);
+    L.Mp = round_up(cost->m + 1, 64);
+    L.Bp = round_up(batch, 32);
+    L.nblk = (L.Np + 255) / 256;
+    pot_problem q;
+    std::memset(&q, 0, sizeof(q));
+    q.n = cost->n;
+    q.m = cost->m;
+    q.kind = cost->kind;
+    q.ldc = cost->ldc;
+    pot_options so;
+    std::memset(&so, 0, sizeof(so));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.solve = take(layout(&q, geometry(&q, &so), nullptr, nullptr));
+    const size_t NM = (size_t)L.Np * L.Mp;
+    L.K = take(2 * NM);
+    L.KT = take(2 * NM);
+    L.abuf = take(4 * 2 * (size_t)L.Bp * L.Np);
+    L.bsc = take(4 * (size_t)L.Bp * L.Mp);
+    L.aop = take(2 * 2 * (size_t)L.Bp * L.Np);
+    L.bop = take(2 * 2 * (size_t)L.Bp * L.Mp);
+    L.P = take(4 * 2 * (size_t)L.Bp * L.Np);
+    L.Q = take(4 * 2 * (size_t)L.Bp * L.Mp);
+    L.rhat = take(4 * (size_t)L.Bp * L.Np);
+    L.chat = take(4 * (size_t)L.Bp * L.Mp);
+    L.errp = take(8 * (size_t)L.Bp * L.nblk);
+    L.done = take(4 * (size_t)L.Bp);
+    L.iters = take(4 * (size_t)L.Bp);
+    L.status = take(4 * (size_t)L.Bp);
+    L.outpar = take(4 * (size_t)L.Bp);
+    L.E = take(8 * (size_t)L.Bp);
+    L.tol = take(8 * (size_t)L.Bp);
+    L.ndone = take(4);
+    L.res = take(sizeof(pot_result) * (size_t)batch);
+    L.total = off;
+    return L;
+}
+
+static pot_status solve_shared(const pot_shared_cost* cost, int batch, const pot_shared_member* mem,
+                               const pot_options* o, void* wsp, size_t ws_bytes, pot_result* res, hipStream_t st) {
+    if (!cost || !mem || !o || !res || batch < 1) return fail(POT_ERR_INVALID_ARG, "cost, members, opts, res and batch >= 1 are required");
+    if (cost->n < 1 || cost->m < 1) return fail(POT_ERR_INVALID_ARG, "n and m must be >= 1");
+    if (cost->kind != POT_COST_F32 && cost->kind != POT_COST_BF16)
+        return fail(POT_ERR_UNSUPPORTED, "the shared cost is dense FP32 or BF16");
+    if (!cost->C || cost->ldc < cost->m) return fail(POT_ERR_INVALID_ARG, "C with ldc >= m is required");
+    if (!std::isfinite(cost->cmax)) return fail(POT_ERR_INVALID_ARG, "cmax not finite");
+    if (o->algo != POT_SINKHORN) return fail(POT_ERR_UNSUPPORTED, "shared-cost batches run feasible Sinkhorn (algo POT_SINKHORN)");
+    if (!(o->gamma > 0.0) || !std::isfinite(o->gamma)) return fail(POT_ERR_INVALID_ARG, "a shared gamma > 0 is required");
+    if (!(o->eps > 0.0) || !std::isfinite(o->eps)) return fail(POT_ERR_INVALID_ARG, "eps must be finite and > 0");
+    if (!std::isfinite(o->tol) || !std::isfinite(o->A)) return fail(POT_ERR_INVALID_ARG, "tol and A must be finite");
+    for (int b = 0; b < batch; ++b)
+        if (!mem[b].r || !mem[b].c) return fail(POT_ERR_INVALID_ARG, "every member needs r and c");
+    const SharedLayout L = shared_layout(cost, batch);
+    if (!wsp || ws_bytes < L.total) return fail(POT_ERR_WORKSPACE, "workspace too small");
+    if (((uintptr_t)wsp) & 255) return fail(POT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    pot_status ps = ensure_poll();
+    if (ps != POT_OK) return ps;
+    char* base = (char*)wsp;
+    const int n = cost->n, m = cost->m, Np = L.Np, Mp = L.Mp, Bp = L.Bp, B = batch;
+
+    // |C|_max (one pass when not given) and the representability of K~
+    double cmax = cost->cmax;
+    if (!(cmax > 0.0)) {
+        unsigned long long* mb = (unsigned long long*)(base + L.errp);
+        HIPCHK(launch_zero_words(mb, 2, st));
+        HIPCHK(launch_cost_max(cost->kind, cost->C, cost->ldc, nullptr, nullptr, n, m, 0, mb, st));
+        unsigned long long h[2];
+        HIPCHK(hipMemcpyAsync(h, mb, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (h[1] != 0) return fail(POT_ERR_INVALID_ARG, "cost has negative or non-finite entries");
+        std::memcpy(&cmax, &h[0], 8);
+        if (!(cmax > 0.0)) return fail(POT_ERR_INVALID_ARG, "cost is identically 0 (|C|_max = 0)");
+    }
+    const double gamma = o->gamma;
+    if (cmax / gamma > 80.0)
+        return fail(POT_ERR_UNSUPPORTED, "max C / gamma > 80: the exponential-domain kernel would underflow "
+                                         "(use pot_solve_batched, which works in the log domain)");
+    const double A = o->A > 0.0 ? o->A : 8.0 * cmax / o->eps;
+
+    uint16_t* K = (uint16_t*)(base + L.K);
+    uint16_t* KT = (uint16_t*)(base + L.KT);
+    float* abuf = (float*)(base + L.abuf);
+    float* bsc = (float*)(base + L.bsc);
+    uint16_t* aop = (uint16_t*)(base + L.aop);
+    uint16_t* bop = (uint16_t*)(base + L.bop);
+    float* P = (float*)(base + L.P);
+    float* Q = (float*)(base + L.Q);
+    float* rhat = (float*)(base + L.rhat);
+    float* chat = (float*)(base + L.chat);
+    double* errp = (double*)(base + L.errp);
+    SharedCtl S;
+    S.done = (int32_t*)(base + L.done);
+    S.iters = (int32_t*)(base + L.iters);
+    S.status = (int32_t*)(base + L.status);
+    S.out_par = (int32_t*)(base + L.outpar);
+    S.E = (double*)(base + L.E);
+    S.tol = (const double*)(base + L.tol);
+    S.ndone = (int32_t*)(base + L.ndone);
+    S.host_done = g_poll.flag;
+    pot_result* resd = (pot_result*)(base + L.res);
+
+    // the operands of padded members and rows stay zero: clear the BF16
+    // operands and scalings once (kernels, not memset nodes)
+    HIPCHK(launch_zero_words((unsigned long long*)aop, (int)(2 * 2 * (size_t)Bp * Np / 8), st));
+    HIPCHK(launch_zero_words((unsigned long long*)bop, (int)(2 * 2 * (size_t)Bp * Mp / 8), st));
+    HIPCHK(launch_zero_words((unsigned long long*)abuf, (int)(4 * 2 * (size_t)Bp * Np / 8), st));
+    HIPCHK(launch_shared_build(cost->kind, cost->C, cost->ldc, n, m, Np, Mp, 1.0 / gamma, std::exp(-A / gamma), K, KT, st));
+    *(volatile int32_t*)g_poll.flag = 0;
+    HIPCHK(launch_shared_init(bsc, bop, m, Mp, B, S, st));
+
+    // the single-instance workspace: each member's setup (smoothing, extension, threshold)
+    pot_problem q;
+    std::memset(&q, 0, sizeof(q));
+    q.n = n; q.m = m; q.kind = cost->kind; q.C = cost->C; q.ldc = cost->ldc;
+    pot_options so;
+    std::memset(&so, 0, sizeof(so));
+    const Geometry g = geometry(&q, &so);
+    Ws w;
+    layout(&q, g, base + L.solve, &w);
+    auto setup_member = [&](int b) -> hipError_t {
+        SetupArgs Sa{};
+        Sa.n = n; Sa.m = m; Sa.algo = POT_SINKHORN; Sa.nx = g.nx; Sa.ny = g.ny;
+        Sa.gamma_rule = 0; Sa.p = 1.0;
+        Sa.s = mem[b].s; Sa.eps = o->eps; Sa.gamma_user = gamma; Sa.tol_user = o->tol; Sa.A_user = A;
+        Sa.cmax = cmax; Sa.cost_scale = 1.0; Sa.w0 = 0.0;
+        Sa.r = mem[b].r; Sa.c = mem[b].c; Sa.maxbuf = nullptr; Sa.kind = cost->kind; Sa.warm = 0;
+        Sa.ws = w;
+        return launch_setup(Sa, st);
+    };
+    for (int b = 0; b < B; ++b) {
+        HIPCHK(setup_member(b));
+        HIPCHK(launch_shared_gather(w, n, m, Np, Mp, b, B, rhat, chat, (double*)S.tol, S, st));
+    }
+
+    // the loop: per iteration two products on the matrix cores, the scaling
+    // updates and the per-member decision; the host reads the pinned flag
+    // after the previous chunk has completed
+    const int max_iter = o->max_iter > 0 ? o->max_iter : 100000;
+    const int chunk = o->check_every > 0 ? o->check_every : 16;
+    bool done = false;
+    int t = 0, k = 0;
+    while (!done && t <= max_iter) {
+        for (int c = 0; c < chunk && t <= max_iter; ++c, ++t) {
+            float* acur = abuf + (size_t)(t & 1) * Bp * Np;
+            float* anext = abuf + (size_t)((t + 1) & 1) * Bp * Np;
+            HIPCHK(launch_shared_gemm(K, bop, P, Np, 2 * Bp, Mp, S.ndone, B, st));
+            HIPCHK(launch_shared_update(P, rhat, acur, anext, aop, n + 1, Np, B, S.done, errp, st));
+            HIPCHK(launch_shared_decide(S, errp, L.nblk, B, t, max_iter, st));
+            HIPCHK(launch_shared_gemm(KT, aop, Q, Mp, 2 * Bp, Np, S.ndone, B, st));
+            HIPCHK(launch_shared_update(Q, chat, bsc, bsc, bop, m + 1, Mp, B, S.done, nullptr, st));
+        }
+        const int slot = k & 1;
+        HIPCHK(hipEventRecord(g_poll.ev[slot], st));
+        if (k > 0) {
+            HIPCHK(hipEventSynchronize(g_poll.ev[slot ^ 1]));
+            done = *(volatile int32_t*)g_poll.flag != 0;
+        }
+        ++k;
+    }
+
+    // per member: its setup again, its output scalings as log-scalings, the
+    // FP64 rounding onto U(r_b, c_b, s_b) and its result block
+    PassArgs Ar;
+    std::memset(&Ar, 0, sizeof(Ar));
+    Ar.C = cost->C; Ar.ldc = cost->ldc; Ar.n = n; Ar.m = m; Ar.kind = cost->kind;
+    Ar.br = g.br; Ar.bc = g.bc; Ar.nx = g.nx; Ar.ny = g.ny;
+    Ar.nrb = (n + 63) / 64; Ar.ncb = (m + 63) / 64;
+    Ar.ws = w;
+    for (int b = 0; b < B; ++b) {
+        HIPCHK(setup_member(b));
+        HIPCHK(launch_shared_load_duals(w, abuf, bsc, n, m, Np, Mp, Bp, b, S, mem[b].f, mem[b].g, st));
+        Ar.r = mem[b].r;
+        Ar.c = mem[b].c;
+        if (!(o->flags & POT_FLAG_NO_ROUND))
+            for (int ph : {PH_R1, PH_R2, PH_R3}) {
+                Ar.phase = ph;
+                HIPCHK(launch_round(Ar, st));
+            }
+        HIPCHK(launch_result(Ar, POT_SINKHORN, resd + b, st));
+    }
+    HIPCHK(hipMemcpyAsync(res, resd, sizeof(pot_result) * (size_t)B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    pot_status first = POT_OK;
+    for (int b = 0; b < B; ++b)
+        if (res[b].status != POT_OK && first == POT_OK) first = (pot_status)res[b].status;
+    if (first != POT_OK) fail(first, "a member of the shared-cost batch did not finish with POT_OK (see res[].status)");
+    else clear_error();
+    return first;
+}
+
 }  // namespace pot
 
 using namespace pot;
@@ -1015,6 +1239,63 @@ pot_status pot_register(const pot_reg_problem* prob, const pot_reg_options* opts
 }
 
 void pot_rigid_align(const double* H, double* R) { rigid_align(H, R); }
+
+pot_status pot_time_shared_gemm(const pot_shared_cost* cost, int32_t batch, double gamma, void* ws, size_t ws_bytes,
+                                int32_t reps, double* med_ms, void* stream) {
+    try {
+        if (!cost || batch < 1 || reps < 1 || !med_ms || !(gamma > 0.0) || !(cost->cmax > 0.0))
+            return fail(POT_ERR_INVALID_ARG, "cost (with cmax), batch >= 1, gamma > 0, reps >= 1 and med_ms are required");
+        if (cost->kind != POT_COST_F32 && cost->kind != POT_COST_BF16) return fail(POT_ERR_UNSUPPORTED, "dense cost");
+        const SharedLayout L = shared_layout(cost, batch);
+        if (!ws || ws_bytes < L.total || (((uintptr_t)ws) & 255)) return fail(POT_ERR_WORKSPACE, "workspace");
+        hipStream_t st = (hipStream_t)stream;
+        char* base = (char*)ws;
+        uint16_t* K = (uint16_t*)(base + L.K);
+        uint16_t* KT = (uint16_t*)(base + L.KT);
+        uint16_t* bop = (uint16_t*)(base + L.bop);
+        float* P = (float*)(base + L.P);
+        int32_t* ndone = (int32_t*)(base + L.ndone);
+        HIPCHK(launch_zero_words((unsigned long long*)bop, (int)(2 * 2 * (size_t)L.Bp * L.Mp / 8), st));
+        HIPCHK(launch_zero_words((unsigned long long*)ndone, 1, st));
+        HIPCHK(launch_shared_build(cost->kind, cost->C, cost->ldc, cost->n, cost->m, L.Np, L.Mp, 1.0 / gamma, 0.0, K, KT,
+                                   st));
+        for (int k = 0; k < 3; ++k) HIPCHK(launch_shared_gemm(K, bop, P, L.Np, 2 * L.Bp, L.Mp, ndone, batch, st));
+        std::vector<hipEvent_t> ev(2 * (size_t)reps);
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        for (int k = 0; k < reps; ++k) {
+            HIPCHK(hipEventRecord(ev[2 * k], st));
+            HIPCHK(launch_shared_gemm(K, bop, P, L.Np, 2 * L.Bp, L.Mp, ndone, batch, st));
+            HIPCHK(hipEventRecord(ev[2 * k + 1], st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<double> t(reps);
+        for (int k = 0; k < reps; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+            t[k] = ms;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        std::sort(t.begin(), t.end());
+        *med_ms = reps % 2 ? t[reps / 2] : 0.5 * (t[reps / 2 - 1] + t[reps / 2]);
+        return POT_OK;
+    } catch (...) {
+        return fail(POT_ERR_DEVICE, "internal error");
+    }
+}
+
+size_t pot_workspace_bytes_shared(const pot_shared_cost* cost, int32_t batch) {
+    if (!cost || cost->n < 1 || cost->m < 1 || batch < 1) return 0;
+    return shared_layout(cost, batch).total;
+}
+
+pot_status pot_solve_shared(const pot_shared_cost* cost, int32_t batch, const pot_shared_member* members,
+                            const pot_options* opts, void* ws, size_t ws_bytes, pot_result* res, void* stream) {
+    try {
+        return solve_shared(cost, batch, members, opts, ws, ws_bytes, res, (hipStream_t)stream);
+    } catch (...) {
+        return fail(POT_ERR_DEVICE, "internal error");
+    }
+}
 
 pot_status pot_solve_noalloc(const pot_problem* prob, const pot_options* opts, pot_result* res,
                              const pot_outputs* out, void* stream) {

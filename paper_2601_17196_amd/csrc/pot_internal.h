@@ -206,6 +206,18 @@ __host__ __device__ inline BLayout blayout(int n, int m, int G) {
     return L;
 }
 
+// per-member state of a shared-cost batch (pot_solve_shared), device arrays
+struct SharedCtl {
+    int32_t* done;         // [B] finished (converged, stopped at max_iter, invalid or not representable)
+    int32_t* iters;        // [B]
+    int32_t* status;       // [B] pot_status
+    int32_t* out_par;      // [B] parity slot of the output row scalings
+    double* E;             // [B] stopping error of the output iterate
+    const double* tol;     // [B] threshold
+    int32_t* ndone;        // [1] members finished
+    int32_t* host_done;    // pinned host flag set when every member has finished, or NULL
+};
+
 // a rigid map F(y) = R y + t (R row-major), passed to kernels by value
 struct RigidMap {
     double R[9];

@@ -78,7 +78,9 @@ __global__ void shared_build_kernel(const void* C, int64_t ldc, int n, int m, in
 // [k + 4 (l >> 4) .. +3] and Bop[col l & 15][same k] and receives
 // Out[col l & 15][rows 4 (l >> 4) .. +3].
 __global__ __launch_bounds__(256) void shared_gemm_kernel(const uint16_t* A, const uint16_t* Bop, float* Out,
-                                                          int rows, int cols, int depth) {
+                                                          int rows, int cols, int depth, const int32_t* ndone,
+                                                          int B) {
+    if (*ndone >= B) return;                 // every member has finished (uniform)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r0 = blockIdx.x * 64 + wave * 16;
     const int c0 = blockIdx.y * 64;
@@ -146,20 +148,16 @@ __global__ __launch_bounds__(256) void shared_update_kernel(const float* prod, c
     }
 }
 
-// Per member: the row error of iterate t (t >= 1) against its threshold;
-// the stop (or max_iter) freezes the member at iterate t.  The last member
-// to finish sets the host flag.
-struct SharedCtl {
-    int32_t* done;         // [B]
-    int32_t* iters;        // [B]
-    int32_t* status;       // [B]
-    int32_t* out_par;      // [B] parity slot of the output scalings
-    double* E;             // [B]
-    const double* tol;     // [B]
-    int32_t* ndone;        // [1]
-    int32_t* host_done;    // pinned host flag, or NULL
-};
 
+// a member has finished: count it; the last one sets the host flag
+__device__ __forceinline__ void member_finished(const SharedCtl& S, int B) {
+    const int k = atomicAdd(S.ndone, 1);
+    if (k + 1 == B && S.host_done) __hip_atomic_store(S.host_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Per member: the row error of iterate t (t >= 1) against its threshold;
+// the stop (or max_iter) freezes the member at iterate t, whose row scalings
+// sit in parity slot t & 1 (the update just made wrote the other one).
 __global__ void shared_decide_kernel(SharedCtl S, const double* err_part, int nblk, int B, int t, int max_iter) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B || S.done[b]) return;
@@ -183,19 +181,27 @@ __global__ void shared_decide_kernel(SharedCtl S, const double* err_part, int nb
     } else {
         return;
     }
-    const int k = atomicAdd(S.ndone, 1);
-    if (k + 1 == B && S.host_done) __hip_atomic_store(S.host_done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    member_finished(S, B);
 }
 
 // Member b's setup results into the batch arrays: r^ and c^ (FP32) and its
-// threshold.  (ws: the single-instance workspace the setup kernel filled.)
-__global__ void shared_gather_kernel(Ws w, int n, int m, int Np, int Mp, int b, float* rhat, float* chat,
-                                     double* tol) {
+// threshold (ws: the single-instance workspace the setup kernel filled).  An
+// invalid member is finished at once with POT_ERR_INVALID_ARG.
+__global__ void shared_gather_kernel(Ws w, int n, int m, int Np, int Mp, int b, int B, float* rhat, float* chat,
+                                     double* tol, SharedCtl S) {
     const Ctl& c = *w.ctl;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < Np) rhat[(int64_t)b * Np + k] = k < n ? (float)w.rt[k] : (k == n ? (float)c.rhat_d : 0.0f);
-    if (k < Mp) chat[(int64_t)b * Mp + k] = k < m ? (float)w.ct[k] : (k == m ? (float)c.chat_d : 0.0f);
-    if (k == 0) tol[b] = c.tol;
+    const bool ok = c.valid == 0;
+    if (k < Np) rhat[(int64_t)b * Np + k] = (ok && k < n) ? (float)w.rt[k] : ((ok && k == n) ? (float)c.rhat_d : 0.0f);
+    if (k < Mp) chat[(int64_t)b * Mp + k] = (ok && k < m) ? (float)w.ct[k] : ((ok && k == m) ? (float)c.chat_d : 0.0f);
+    if (k == 0) {
+        tol[b] = c.tol;
+        if (!ok) {
+            S.done[b] = 1;
+            S.status[b] = POT_ERR_INVALID_ARG;
+            member_finished(S, B);
+        }
+    }
 }
 
 // Start of the loop: b = 1 on every real and dummy column (log b = 0, the
@@ -228,15 +234,16 @@ __global__ void shared_load_duals_kernel(Ws w, const float* abuf, const float* b
     Ctl& c = *w.ctl;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const float* a = abuf + ((int64_t)S.out_par[b] * Bp + b) * Np;
+    const bool out = S.status[b] != POT_ERR_INVALID_ARG;    // an invalid member gets no output
     if (k < n) {
         const double f = log((double)a[k]);
         w.ubar[k] = f;
-        if (fo) fo[k] = f;
+        if (fo && out) fo[k] = f;
     }
     if (k < m) {
         const double g = log((double)bsc[(int64_t)b * Mp + k]);
         w.vbar[k] = g;
-        if (go) go[k] = g;
+        if (go && out) go[k] = g;
     }
     if (k == 0) {
         c.done = 1;
@@ -264,8 +271,8 @@ hipError_t launch_shared_build(int kind, const void* C, int64_t ldc, int n, int 
 }
 
 hipError_t launch_shared_gemm(const uint16_t* A, const uint16_t* Bop, float* Out, int rows, int cols, int depth,
-                              hipStream_t st) {
-    shared_gemm_kernel<<<dim3(rows / 64, cols / 64), 256, 0, st>>>(A, Bop, Out, rows, cols, depth);
+                              const int32_t* ndone, int B, hipStream_t st) {
+    shared_gemm_kernel<<<dim3(rows / 64, cols / 64), 256, 0, st>>>(A, Bop, Out, rows, cols, depth, ndone, B);
     return hipGetLastError();
 }
 
@@ -275,10 +282,10 @@ hipError_t launch_shared_update(const float* prod, const float* mass, const floa
     return hipGetLastError();
 }
 
-hipError_t launch_shared_gather(const Ws& w, int n, int m, int Np, int Mp, int b, float* rhat, float* chat, double* tol,
-                                hipStream_t st) {
+hipError_t launch_shared_gather(const Ws& w, int n, int m, int Np, int Mp, int b, int B, float* rhat, float* chat,
+                                double* tol, const SharedCtl& S, hipStream_t st) {
     const int len = Np > Mp ? Np : Mp;
-    shared_gather_kernel<<<(len + 255) / 256, 256, 0, st>>>(w, n, m, Np, Mp, b, rhat, chat, tol);
+    shared_gather_kernel<<<(len + 255) / 256, 256, 0, st>>>(w, n, m, Np, Mp, b, B, rhat, chat, tol, S);
     return hipGetLastError();
 }
 

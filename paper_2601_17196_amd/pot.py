@@ -17,7 +17,7 @@ __all__ = [
     "load", "lib_path", "ASPOT", "SINKHORN", "COST_F32", "COST_BF16", "COST_POINTS",
     "FLAG_WANT_PLAN", "FLAG_NO_ROUND", "Problem", "Options", "Result", "Outputs",
     "solve", "solve_batched", "workspace_bytes", "status_string", "last_error", "SolveOutput",
-    "PotError", "time_pass", "result_from_device", "FLAG_ASYNC", "register", "rigid_align",
+    "PotError", "time_pass", "result_from_device", "FLAG_ASYNC", "register", "rigid_align", "solve_shared", "time_shared_gemm", "workspace_bytes_shared",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -89,6 +89,15 @@ class Outputs(ct.Structure):
                 ("moments", ct.c_void_p)]
 
 
+class SharedCost(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("m", ct.c_int32), ("kind", ct.c_int32), ("pad", ct.c_int32),
+                ("C", ct.c_void_p), ("ldc", ct.c_int64), ("cmax", ct.c_double)]
+
+
+class SharedMember(ct.Structure):
+    _fields_ = [("r", ct.c_void_p), ("c", ct.c_void_p), ("s", ct.c_double), ("f", ct.c_void_p), ("g", ct.c_void_p)]
+
+
 class RegProblem(ct.Structure):
     _fields_ = [("n", ct.c_int32), ("m", ct.c_int32), ("x", ct.c_void_p), ("y", ct.c_void_p),
                 ("r", ct.c_void_p), ("c", ct.c_void_p), ("s", ct.c_double), ("cost_scale", ct.c_double)]
@@ -146,6 +155,14 @@ def load():
     lib.pot_solve_noalloc.argtypes = [ct.POINTER(Problem), ct.POINTER(Options), ct.POINTER(Result),
                                       ct.POINTER(Outputs), ct.c_void_p]
     lib.pot_solve_noalloc.restype = ct.c_int
+    lib.pot_workspace_bytes_shared.argtypes = [ct.POINTER(SharedCost), ct.c_int32]
+    lib.pot_workspace_bytes_shared.restype = ct.c_size_t
+    lib.pot_solve_shared.argtypes = [ct.POINTER(SharedCost), ct.c_int32, ct.POINTER(SharedMember), ct.POINTER(Options),
+                                     ct.c_void_p, ct.c_size_t, ct.POINTER(Result), ct.c_void_p]
+    lib.pot_solve_shared.restype = ct.c_int
+    lib.pot_time_shared_gemm.argtypes = [ct.POINTER(SharedCost), ct.c_int32, ct.c_double, ct.c_void_p, ct.c_size_t,
+                                         ct.c_int32, ct.POINTER(ct.c_double), ct.c_void_p]
+    lib.pot_time_shared_gemm.restype = ct.c_int
     lib.pot_register_workspace_bytes.argtypes = [ct.POINTER(RegProblem)]
     lib.pot_register_workspace_bytes.restype = ct.c_size_t
     lib.pot_register.argtypes = [ct.POINTER(RegProblem), ct.POINTER(RegOptions), ct.c_void_p, ct.c_size_t,
@@ -335,6 +352,77 @@ def solve(r, c, s, eps, C=None, x=None, y=None, kind=None, ldc=None, cost_scale=
     if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
         raise PotError(st, last_error())
     return so
+
+
+def solve_shared(C, members, eps, gamma, tol=0.0, A=0.0, max_iter=100000, kind=None, ldc=None, cmax=0.0,
+                 want_duals=True, flags=0, stream=None, workspace=None, raise_on_error=False):
+    """Feasible Sinkhorn for many members on one shared cost
+    (pot_solve_shared).  C: (n, ldc) float32 or BF16 bit patterns on the GPU;
+    members: list of dicts with r, c (device float64) and s.  Returns
+    (status, list of result dicts, list of (f, g) or None)."""
+    import torch
+    lib = load()
+    n, m = int(members[0]["r"].shape[0]), int(members[0]["c"].shape[0])
+    B = len(members)
+    cost = _shared_cost(C, cmax, kind, ldc)
+    mem = (SharedMember * B)()
+    outs = []
+    dev = C.device
+    for k, d in enumerate(members):
+        mem[k].r, mem[k].c, mem[k].s = _ptr(d["r"]), _ptr(d["c"]), float(d["s"])
+        if want_duals:
+            f = torch.empty(n, dtype=torch.float64, device=dev)
+            g = torch.empty(m, dtype=torch.float64, device=dev)
+            mem[k].f, mem[k].g = _ptr(f), _ptr(g)
+            outs.append((f, g))
+    opts = make_options(eps, algo=SINKHORN, gamma=gamma, tol=tol, A=A, max_iter=max_iter, flags=flags)
+    nbytes = int(lib.pot_workspace_bytes_shared(ct.byref(cost), B))
+    if nbytes == 0:
+        raise PotError(ERR_INVALID_ARG, "invalid sizes")
+    if workspace is None or workspace.numel() < nbytes + 256:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    aligned = (workspace.data_ptr() + 255) & ~255
+    res = (Result * B)()
+    st = lib.pot_solve_shared(ct.byref(cost), B, mem, ct.byref(opts), ct.c_void_p(aligned),
+                              ct.c_size_t(workspace.numel() - (aligned - workspace.data_ptr())), res,
+                              _stream_ptr(stream))
+    if raise_on_error and st not in (OK, ERR_NO_CONVERGENCE):
+        raise PotError(st, last_error())
+    return int(st), [res[k].as_dict() for k in range(B)], (outs if want_duals else None)
+
+
+def _shared_cost(C, cmax=0.0, kind=None, ldc=None):
+    import torch
+    cost = SharedCost()
+    cost.n, cost.m = int(C.shape[0]), int(C.shape[1])
+    cost.kind = (COST_F32 if C.dtype == torch.float32 else COST_BF16) if kind is None else int(kind)
+    cost.C = _ptr(C)
+    cost.ldc = int(ldc if ldc is not None else C.stride(0))
+    cost.cmax = float(cmax)
+    return cost
+
+
+def workspace_bytes_shared(C, batch, kind=None, ldc=None) -> int:
+    return int(load().pot_workspace_bytes_shared(ct.byref(_shared_cost(C, 0.0, kind, ldc)), int(batch)))
+
+
+def time_shared_gemm(C, batch, gamma, cmax, reps=20, stream=None):
+    """Median time (ms) of the shared-cost product K~ x scalings for
+    `batch` members (pot_time_shared_gemm) and the padded sizes
+    (rows, cols, depth)."""
+    import torch
+    lib = load()
+    cost = _shared_cost(C, cmax)
+    nbytes = int(lib.pot_workspace_bytes_shared(ct.byref(cost), int(batch)))
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=C.device)
+    aligned = (ws.data_ptr() + 255) & ~255
+    ms = ct.c_double(0.0)
+    st = lib.pot_time_shared_gemm(ct.byref(cost), int(batch), float(gamma), ct.c_void_p(aligned), ct.c_size_t(nbytes),
+                                  int(reps), ct.byref(ms), _stream_ptr(stream))
+    if st != OK:
+        raise PotError(st, last_error())
+    up = lambda x, k: (x + k - 1) // k * k
+    return ms.value, (up(cost.n + 1, 64), 2 * up(int(batch), 32), up(cost.m + 1, 64))
 
 
 def rigid_align(H):

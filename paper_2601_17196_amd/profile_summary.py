@@ -20,11 +20,14 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/pot_kernels.hip", "csrc/pot_device.h", "csrc/pot_internal.h"]
+BATCHED_SOURCES = ["csrc/pot_batched.hip", "csrc/pot_device.h", "csrc/pot_internal.h"]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=None) -> str:
+    """Hash of the sources a kernel is built from (default: the
+    single-instance kernels)."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (files or KERNEL_SOURCES):
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -58,7 +61,7 @@ def per_kernel(path, counter):
     return out
 
 
-def pmc_summary(fetch_csv, write_csv, copy_bytes, copy_pattern, kernel_pattern, command):
+def pmc_summary(fetch_csv, write_csv, copy_bytes, copy_pattern, kernel_pattern, command, sources=None):
     f = per_kernel(fetch_csv, "FETCH_SIZE")
     w = per_kernel(write_csv, "WRITE_SIZE")
 
@@ -79,7 +82,8 @@ def pmc_summary(fetch_csv, write_csv, copy_bytes, copy_pattern, kernel_pattern, 
            "scale_fetch": sf, "scale_write": sw,
            "fetch_bytes": kf * 1024.0 * sf if kf and sf else None,
            "write_bytes": kw * 1024.0 * sw if kw and sw else None,
-           "kernel_source_hash": kernel_source_hash(), "command": command}
+           "kernel_sources": sources or KERNEL_SOURCES,
+           "kernel_source_hash": kernel_source_hash(sources), "command": command}
     if out["fetch_bytes"] is not None and out["write_bytes"] is not None:
         out["traffic_bytes"] = out["fetch_bytes"] + out["write_bytes"]
     return out
@@ -101,11 +105,13 @@ def main():
     p.add_argument("--kernel-pattern", required=True)
     p.add_argument("--command", required=True)
     p.add_argument("--out", required=True)
+    p.add_argument("--batched", action="store_true", help="the kernel is the batched one (its own sources)")
     a = ap.parse_args()
     if a.mode == "stats":
         open(a.out, "w").write(stats_table(a.csv, a.title, a.command))
     else:
-        res = pmc_summary(a.fetch_csv, a.write_csv, a.copy_bytes, a.copy_pattern, a.kernel_pattern, a.command)
+        res = pmc_summary(a.fetch_csv, a.write_csv, a.copy_bytes, a.copy_pattern, a.kernel_pattern, a.command,
+                          BATCHED_SOURCES if a.batched else None)
         json.dump(res, open(a.out, "w"), indent=1)
     print(open(a.out).read())
 
