@@ -238,9 +238,9 @@ size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, cons
  * dense POT_COST_F32 or POT_COST_BF16 cost (the same kind for the whole
  * batch) with 1 <= n, m <= 1024; the algorithm, its defaults and the
  * rounding are those of pot_solve, per instance.  Workgroups take instances
- * from a device queue, largest first; an instance with more than
- * opts->member_elems cost entries is split by rows over a group of up to 8
- * workgroups.  probs (host array) describe the instances with device
+ * from a device queue, largest first (ties: larger s first); an instance
+ * with more than opts->member_elems cost entries is split by rows over a
+ * group of up to 8 workgroups.  probs (host array) describe the instances with device
  * pointers (cmax <= 0: scanned on the device); opts apply to all (force and
  * trace must be NULL; tile_rows is ignored); warm (may be NULL) gives
  * per-instance warm starts; res (host array of batch) receives the results
@@ -342,7 +342,7 @@ pot_status pot_solve_shared(const pot_shared_cost* cost, int32_t batch, const po
 
 /* Measurement hook: build K~ for the shared cost (cmax and gamma given) and
  * time the first product of an iteration, K~ times every member's split
- * scalings (rows x 2 batch x columns, padded to multiples of 64 and 32
+ * scalings (rows x 2 batch x columns, padded to multiples of 64 and 64
  * members), 3 untimed and then `reps` times with HIP events around each
  * launch; *med_ms receives the median.  Writes only the workspace
  * (pot_workspace_bytes_shared).  Synchronises the stream. */

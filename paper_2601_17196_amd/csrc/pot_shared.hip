@@ -22,7 +22,8 @@
 //
 // Layout: K~ [Np][Mp] and its transpose [Mp][Np], BF16, zero padded to
 // multiples of 64; the scalings [Bp][Np] and [Bp][Mp] (FP32, instance-major);
-// the BF16 operands [2 Bp][Mp] and [2 Bp][Np] (hi row, lo row per member);
+// the BF16 operands [2 Bp][Mp] and [2 Bp][Np] (hi row, lo row per member; Bp
+// a multiple of 64);
 // GEMM outputs [2 Bp][Np] / [2 Bp][Mp] FP32.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -72,44 +73,93 @@ __global__ void shared_build_kernel(const void* C, int64_t ldc, int n, int m, in
 }
 
 // Out[q][i] = sum_k A[i][k] Bop[q][k] for i < rows (multiple of 64), q < cols
-// (multiple of 64), K = depth (multiple of 16): 256 threads, a 64 x 64 tile
-// per workgroup, each wave 16 rows x 64 columns as four 16 x 16 MFMA tiles
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation).  Lane l holds A[row l & 15]
-// [k + 4 (l >> 4) .. +3] and Bop[col l & 15][same k] and receives
-// Out[col l & 15][rows 4 (l >> 4) .. +3].
+// (multiple of TN), k < depth (multiple of 32): both operands K-contiguous,
+// BF16, FP32 accumulation on v_mfma_f32_16x16x16_bf16.  A 256-thread
+// workgroup owns a 64 x TN output tile (waves 2 x 2, each 32 x TN/2 = 2 x
+// TN/32 MFMA tiles); TN = 128 where that still gives a workgroup per compute
+// unit, else 64.  Per step of 32 k, every thread brings one 16-byte chunk of
+// the A tile and TN/64 of the B tile into registers (the next step's, while
+// the current step computes) and stores them to LDS, laid out [k-group of
+// 4][row] in 8-byte entries, so that a fragment read (16 rows x 4 k-groups)
+// is one ds_read_b64 per lane; two LDS buffers alternate.  MFMA lane layout:
+// lane l holds A[row l & 15][k-group l >> 4] and B[col l & 15][k-group l >> 4]
+// and receives Out[col l & 15][rows 4 (l >> 4) .. +3].
+constexpr int kGM = 64, kGK = 32, kGPad = 4;
+template <int TN>
 __global__ __launch_bounds__(256) void shared_gemm_kernel(const uint16_t* A, const uint16_t* Bop, float* Out,
                                                           int rows, int cols, int depth, const int32_t* ndone,
                                                           int B) {
+    constexpr int NB = TN / 64, NT = TN / 32;
     if (*ndone >= B) return;                 // every member has finished (uniform)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = blockIdx.x * 64 + wave * 16;
-    const int c0 = blockIdx.y * 64;
-    const int kq = 4 * (lane >> 4);
-    const uint16_t* arow = A + (int64_t)(r0 + (lane & 15)) * depth + kq;
-    const uint16_t* bcol[4];
+    __shared__ uint2 As[2][kGK / 4][kGM + kGPad];
+    __shared__ uint2 Bs[2][kGK / 4][TN + kGPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int i0 = blockIdx.x * kGM, q0 = blockIdx.y * TN;
+    // global -> register chunks: A row tid >> 2, chunk tid & 3; B rows 64 h + (tid >> 2)
+    const int lr = tid >> 2, lc = tid & 3;
+    const uint4* ag = (const uint4*)(A + (int64_t)(i0 + lr) * depth + 8 * lc);
+    const uint4* bg[NB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) bcol[t] = Bop + (int64_t)(c0 + 16 * t + (lane & 15)) * depth + kq;
-    f32x4v acc[4];
+    for (int h = 0; h < NB; ++h) bg[h] = (const uint4*)(Bop + (int64_t)(q0 + 64 * h + lr) * depth + 8 * lc);
+    uint4 ra, rb[NB];
+    auto fetch = [&](int off) __attribute__((always_inline)) {
+        ra = ag[off];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f32x4v{0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < depth; k += 64) {
-        bf16x4 a[4], b[4][4];
+        for (int h = 0; h < NB; ++h) rb[h] = bg[h][off];
+    };
+    auto to_lds = [&](int buf) __attribute__((always_inline)) {
+        As[buf][2 * lc][lr] = make_uint2(ra.x, ra.y);
+        As[buf][2 * lc + 1][lr] = make_uint2(ra.z, ra.w);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = *(const bf16x4*)(arow + k + 16 * u);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) b[u][t] = *(const bf16x4*)(bcol[t] + k + 16 * u);
+        for (int h = 0; h < NB; ++h) {
+            Bs[buf][2 * lc][64 * h + lr] = make_uint2(rb[h].x, rb[h].y);
+            Bs[buf][2 * lc + 1][64 * h + lr] = make_uint2(rb[h].z, rb[h].w);
         }
+    };
+    f32x4v acc[2][NT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+    for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b[u][t], acc[t], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4v{0.f, 0.f, 0.f, 0.f};
+    const int nk = depth / kGK;
+    fetch(0);
+    to_lds(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) fetch((kt + 1) * kGK / 8);      // offset in 16-byte chunks
+#pragma unroll
+        for (int ks = 0; ks < kGK / 16; ++ks) {
+            const int kg = 4 * ks + (lane >> 4);
+            bf16x4 af[2], bf[NT];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const uint2 v = As[buf][kg][32 * wm + 16 * mt + (lane & 15)];
+                af[mt] = *(const bf16x4*)&v;
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const uint2 v = Bs[buf][kg][(TN / 2) * wn + 16 * nt + (lane & 15)];
+                bf[nt] = *(const bf16x4*)&v;
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
+        }
+        if (kt + 1 < nk) to_lds(buf ^ 1);
+        __syncthreads();
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        float* o = Out + (int64_t)(c0 + 16 * t + (lane & 15)) * rows + r0 + kq;
-        *(f32x4v*)o = acc[t];
-    }
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            float* o = Out + (int64_t)(q0 + (TN / 2) * wn + 16 * nt + (lane & 15)) * rows + i0 + 32 * wm + 16 * mt +
+                       4 * (lane >> 4);
+            *(f32x4v*)o = acc[mt][nt];
+        }
 }
 
 // The scaling update of one side for every member: s_new = mass / (sum of
@@ -272,7 +322,11 @@ hipError_t launch_shared_build(int kind, const void* C, int64_t ldc, int n, int 
 
 hipError_t launch_shared_gemm(const uint16_t* A, const uint16_t* Bop, float* Out, int rows, int cols, int depth,
                               const int32_t* ndone, int B, hipStream_t st) {
-    shared_gemm_kernel<<<dim3(rows / 64, cols / 64), 256, 0, st>>>(A, Bop, Out, rows, cols, depth, ndone, B);
+    if (rows % kGM || cols % 64 || depth % kGK) return hipErrorInvalidValue;
+    if (cols % 128 == 0 && (int64_t)(rows / kGM) * (cols / 128) >= 256)
+        shared_gemm_kernel<128><<<dim3(rows / kGM, cols / 128), 256, 0, st>>>(A, Bop, Out, rows, cols, depth, ndone, B);
+    else
+        shared_gemm_kernel<64><<<dim3(rows / kGM, cols / 64), 256, 0, st>>>(A, Bop, Out, rows, cols, depth, ndone, B);
     return hipGetLastError();
 }
 

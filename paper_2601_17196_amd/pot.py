@@ -422,7 +422,7 @@ def time_shared_gemm(C, batch, gamma, cmax, reps=20, stream=None):
     if st != OK:
         raise PotError(st, last_error())
     up = lambda x, k: (x + k - 1) // k * k
-    return ms.value, (up(cost.n + 1, 64), 2 * up(int(batch), 32), up(cost.m + 1, 64))
+    return ms.value, (up(cost.n + 1, 64), 2 * up(int(batch), 64), up(cost.m + 1, 64))
 
 
 def rigid_align(H):
