@@ -197,6 +197,61 @@ __device__ __forceinline__ double group16_sum(double v) {
     return v;
 }
 
+// Sixteen values summed over the 64 lanes of a wave, all together: the two
+// lane swaps above halve the values each lane carries twice (16 -> 8 -> 4),
+// then two exchanges inside 16-lane rows (row_mirror, row_half_mirror: a lane
+// keeps one of each pair of values and adds its partner's copy of it) halve
+// them to one, and two quad steps finish the sum.  Lane l ends with the total
+// of value 8 b2 + 4 b3 + 2 b4 + b5 (b_k: bit k of l).  Fixed order.
+__device__ __forceinline__ double wave_sum16(const double (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+    double w[8], x[4], y[2];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = swap32_add(v[2 * i], v[2 * i + 1]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = swap16_add(w[2 * i], w[2 * i + 1]);
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = b3 ? x[2 * i + 1] : x[2 * i], send = b3 ? x[2 * i] : x[2 * i + 1];
+        y[i] = keep + dpp_d<kMirror>(send, 0.0);
+    }
+    const double keep = b2 ? y[1] : y[0], send = b2 ? y[0] : y[1];
+    double z = keep + dpp_d<kHalfMirror>(send, 0.0);
+    z += dpp_d<kQuadX1>(z, 0.0);
+    z += dpp_d<kQuadX2>(z, 0.0);
+    return z;
+}
+
+// The row-side and column-side scalars of the steps (kScal each) summed over
+// the workgroup; the totals land on every lane of wave 0 (the lanes that
+// exchange and decide).  The waves' totals pass through the column-partial
+// area, free once the column sums are formed.
+__device__ __forceinline__ void block_sum_rc(double (&Rs)[kScal], double (&Cs)[kScal], BShared& S) {
+    static_assert(kScal == 8, "16 values per lane");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = Rs[k];
+        v[8 + k] = Cs[k];
+    }
+    const double z = wave_sum16(v);
+    const int q = lane >> 2;
+    const int idx = ((q & 1) << 3) | ((q & 2) << 1) | ((q & 4) >> 1) | ((q & 8) >> 3);
+    double* red = &S.colw[0][0];
+    if ((lane & 3) == 0) red[wave * 16 + idx] = z;
+    __syncthreads();
+    if (wave == 0) {
+        const double t = wave_tree<kBWaves>(red + (lane & 15), 16);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            Rs[k] = readlane_d(t, k);
+            Cs[k] = readlane_d(t, 8 + k);
+        }
+    }
+}
+
 template <int U>
 __device__ __forceinline__ void rows_reduce(const double (&rs)[U], double (&out)[(U + 3) / 4]) {
     static_assert(U == 2 || U == 4 || U == 8, "rows per step");
@@ -454,8 +509,7 @@ __device__ bool member_pass(Member& M, BShared& S) {
                 aspot_step<PH>(A, false, j, S.Q[j], Ke, 0.0, p, Cs);
             }
         }
-        block_sum<kScal, kBWaves>(Rs, S.red);
-        block_sum<kScal, kBWaves>(Cs, S.red);
+        block_sum_rc(Rs, Cs, S);
     }
     // ---- row-side scalars of the whole instance (fixed member order)
     if (ROWS && M.G > 1) {
