@@ -487,7 +487,7 @@ def bench_tracking(pot, I, dev, eps, count=1024, reps=3):
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
-def bench_shared(pot, dev, eps, n=1024, B=256):
+def bench_shared(pot, dev, eps, n=4096, B=256):
     """Shared-cost batch (pot_solve_shared): B members with their own
     Dirichlet marginals and s on one n x n cost (2-D uniform points), gamma =
     max C / 60; members/s, and the matrix-core product's roofline (2 x rows x
@@ -531,7 +531,7 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--pmc-probe", choices=["none", "c5", "c3f32", "c3bf16", "c2"], default="none",
+    ap.add_argument("--pmc-probe", choices=["none", "c5", "c3f32", "c3bf16", "c2", "shared"], default="none",
                     help="profiling workload only: a 256 MiB device copy (the counters' scale), then the named "
                          "workload's kernel once or a few times; prints no JSON line")
     args = ap.parse_args()
@@ -558,6 +558,8 @@ def main():
         del a, b
         if args.pmc_probe == "c5":
             headline(pot, I, dev, eps, 1, 0, 0, 1)
+        elif args.pmc_probe == "shared":
+            log(f"shared: {bench_shared(pot, dev, eps)}")
         elif args.pmc_probe == "c2":
             inst = I.c2(0, n=4096)
             d = pot.to_device_instance(inst, dev, kind="f32")
@@ -597,9 +599,9 @@ def main():
         log("registration: 4096 / 2048 points, warm vs cold")
         extra["registration_4096x2048"] = bench_register(pot, dev, eps)
         log(f"registration: {extra['registration_4096x2048']}")
-        log("shared cost: 256 members on one 1024^2 cost")
-        extra["shared_cost_1024_x256"] = bench_shared(pot, dev, eps)
-        log(f"shared: {extra['shared_cost_1024_x256']}")
+        log("shared cost: 256 members on one 4096^2 cost")
+        extra["shared_cost_4096_x256"] = bench_shared(pot, dev, eps)
+        log(f"shared: {extra['shared_cost_4096_x256']}")
         log("shard: rows 0..2499 of the 20000^2 instance (one GPU of 8)")
         extra["c3_shard_2500x20000"] = bench_shard(pot, I, dev, eps, args.reps)
         log(f"shard: {extra['c3_shard_2500x20000']}")
