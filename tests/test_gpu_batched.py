@@ -214,3 +214,44 @@ def test_batched_uneven_batch_full_size():
         gaps.append(info["gap"])
     print(f"c4: 512 instances through the oracle, largest |E_gpu - E_oracle| {worst:.3e}, "
           f"cost - lower bound: median {np.median(gaps):.2e} max {np.max(gaps):.2e}", flush=True)
+
+
+def test_batched_tracking_warm_start():
+    """Warm starts from a previous solve (the tracking use of the benchmark):
+    four instances of the 256 x 256 mixture batch are solved cold, every
+    target cloud is moved by a small rigid step (1 degree about its centroid,
+    shift 0.005, the cost renormalised to max 1), and the moved instances are solved from
+    the first solve's duals with the phi check.  Every warm start is kept,
+    every moved instance passes Definition 1 (E recomputed by the oracle at
+    the GPU's output point, the oracle's rounding of the GPU's duals, and
+    cost - LB <= eps for the weak-duality bound from the GPU's duals), and the
+    warm solves take fewer iterations in total than the cold ones."""
+    base = I.c5_batch(4)
+    st0, res0, fg0 = _solve(base, "aspot")
+    assert st0 == 0
+    th = np.deg2rad(1.0)
+    Rz = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    moved = []
+    for inst in base:
+        y = inst.y.astype(np.float64)
+        mu = y.mean(0)
+        y2 = ((y - mu) @ Rz.T + mu + 0.005).astype(np.float32).astype(np.float64)
+        D = ((inst.x.astype(np.float64)[:, None, :] - y2[None, :, :]) ** 2).sum(-1)
+        C = D / D.max()
+        mv = I.Instance(x=inst.x, y=y2.astype(np.float32), r=inst.r, c=inst.c, s=inst.s, cost_scale=1.0 / D.max(),
+                        C64=C, C32=np.ascontiguousarray(C.astype(np.float32)), eps=inst.eps,
+                        name=inst.name + " moved")
+        moved.append(mv)
+    u0 = [fg[2] for fg in fg0]
+    v0 = [fg[3] for fg in fg0]
+    w0 = [r["w"] for r in res0]
+    stw, resw, fgw = _solve(moved, "aspot", u0=u0, v0=v0, w0=w0, warm_check=True)
+    stc, resc, _ = _solve(moved, "aspot")
+    assert stw == 0 and stc == 0
+    for inst, r, fg in zip(moved, resw, fgw):
+        assert r["used_warm"] == 1, (inst.name, r)
+        check_definition1_batched(inst, "f32", "aspot", r, *fg, dual=True)
+    itw = sum(r["iters"] for r in resw)
+    itc = sum(r["iters"] for r in resc)
+    print(f"tracking: warm {itw} vs cold {itc} iterations", flush=True)
+    assert itw < itc
