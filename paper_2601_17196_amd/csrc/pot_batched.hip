@@ -170,25 +170,13 @@ __device__ __forceinline__ void unpack_chunk(const f32x4& q, float (&cv)[VW]) {
 
 // Row sums of a sweep step, reduced together.  Each lane holds a partial
 // sum of each of the step's U rows.  A swap of the upper and lower 32 lanes
-// between two rows' registers (v_permlane32_swap) and one add leave row a in
-// lanes 0-31 and row b in lanes 32-63, each lane summing two; a swap of odd
-// and even 16-lane groups between two such results (v_permlane16_swap) leaves
-// one row per 16-lane group, each lane summing four; four DPP steps then add
-// the group.  Every lane of group g ends with the total of one row:
+// between two rows' registers (swap32_add) and one add leave row a in lanes
+// 0-31 and row b in lanes 32-63, each lane summing two; a swap of odd and
+// even 16-lane groups between two such results (swap16_add) leaves one row
+// per 16-lane group, each lane summing four; four DPP steps then add the
+// group.  Every lane of group g ends with the total of one row:
 //   U >= 4: row 4h + ((g & 1) << 1 | g >> 1) in out[h];  U = 2: row g >> 1.
 // The order of the additions is fixed (bitwise reproducible).
-__device__ __forceinline__ double swap32_add(double x, double y) {
-    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
-__device__ __forceinline__ double swap16_add(double x, double y) {
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
 __device__ __forceinline__ double group16_sum(double v) {
     v += dpp_d<kQuadX1>(v, 0.0);
     v += dpp_d<kQuadX2>(v, 0.0);

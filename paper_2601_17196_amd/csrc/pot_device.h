@@ -43,6 +43,45 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
+// Lane swaps of gfx950 (v_permlane32_swap, v_permlane16_swap) for reducing
+// several values at once.  swap32_add(x, y): lanes 0-31 get x summed over
+// lanes l and l + 32, lanes 32-63 get y summed likewise; swap16_add(x, y):
+// the even 16-lane groups get x summed over a group and the next, the odd
+// groups get y.  Fixed order.
+__device__ __forceinline__ double swap32_add(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+__device__ __forceinline__ double swap16_add(double x, double y) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Eight values summed over the 64 lanes of a wave, all together: two swaps
+// (8 -> 4 -> 2 values per lane), one exchange inside 16-lane rows
+// (row_mirror: a lane keeps one of the two values and adds its partner's
+// copy of it), then row_half_mirror and two quad steps finish the sum.  Lane
+// l ends with the total of value 4 b3 + 2 b4 + b5 (b_k: bit k of l); lane 8 j
+// holds value ((j & 1) << 2) | (j & 2) | (j >> 2).  Fixed order.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
+    const int lane = threadIdx.x & 63;
+    double w[4], x[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = swap32_add(v[2 * i], v[2 * i + 1]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) x[i] = swap16_add(w[2 * i], w[2 * i + 1]);
+    const bool b3 = (lane & 8) != 0;
+    const double keep = b3 ? x[1] : x[0], send = b3 ? x[0] : x[1];
+    double z = keep + dpp_d<kMirror>(send, 0.0);
+    z += dpp_d<kHalfMirror>(z, 0.0);
+    z += dpp_d<kQuadX1>(z, 0.0);
+    z += dpp_d<kQuadX2>(z, 0.0);
+    return z;
+}
+
 // fixed combination order: deterministic; the total is returned to every lane
 __device__ __forceinline__ double wave_sum(double v) {
     v += dpp_d<kQuadX1>(v, 0.0);

@@ -678,10 +678,14 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
             }
             if (tid < len)
                 aspot_step<PHASE>(A, is_row, base + tid, Rm, Re, ldexp(Rm, Re - (int)eref), pre, sums);
+            // the block's sums, all slots over the wave at once (no barrier:
+            // the other waves hold nothing); lane 8 j stores one slot
+            const double z = wave_sum8(sums);
+            if ((tid & 7) == 0) {
+                const int j = tid >> 3, k = ((j & 1) << 2) | (j & 2) | (j >> 2);
+                st_agent(&out[k], k == 6 ? (is_row ? eref : 0.0) : z);
+            }
         }
-        block_sum<kScal>(sums, s_red);
-        if (tid == 0)
-            for (int k = 0; k < kScal; ++k) st_agent(&out[k], k == 6 ? (is_row ? eref : 0.0) : sums[k]);
     }
     // arrival: the last block decides
     wait_stores();
