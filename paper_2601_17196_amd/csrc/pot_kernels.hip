@@ -594,7 +594,6 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
     __shared__ double s_part[4][kFinBlock];
     __shared__ int s_pe[4][kFinBlock];
     __shared__ double s_v[kFinBlock];
-    __shared__ int s_ve[kFinBlock];
     __shared__ double s_red[4 * 2 * kScal];
     __shared__ int s_last;
     __shared__ Ctl s_ctl;                              // snapshot of the control block
@@ -638,7 +637,12 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
         __syncthreads();
     }
     // the quarters combined in a fixed order, on the largest exponent (the
-    // rescalings are exact: in the FP64 range these are the plain sums)
+    // rescalings are exact: in the FP64 range these are the plain sums).
+    // An ASPOT pass keeps them in wave 0's registers (the lanes that step
+    // them); a Sinkhorn pass shares them through LDS.
+    constexpr bool skp = PHASE == PH_SK_ROW || PHASE == PH_SK_COL;
+    double Rv = 0.0;
+    int Re = 0;
     if (tid < kFinBlock) {
         int e = 0;
         double v;
@@ -651,11 +655,11 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
             if (e == kNoExp) e = 0;
         }
         // (the Sinkhorn steps take the value itself)
-        const bool skp = PHASE == PH_SK_ROW || PHASE == PH_SK_COL;
-        s_v[tid] = skp ? ldexp(v, e) : v;
-        s_ve[tid] = skp ? 0 : e;
+        if (skp) s_v[tid] = ldexp(v, e);
+        Rv = v;
+        Re = e;
     }
-    __syncthreads();
+    if (skp) __syncthreads();
     double* out = (is_row ? A.ws.rowscal + (int64_t)blk * kScal : A.ws.colscal + (int64_t)cb * kScal);
     if constexpr (PHASE == PH_SK_ROW) {
         sk_row_finalise(A, c, base, len, s_v, pre, out, s_red);
@@ -669,8 +673,7 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
         // the largest exponent of the block's row sums (slot 6)
         double eref = 0.0;
         if (tid < kFinBlock) {       // wave 0: the block's rows or columns
-            const double Rm = s_v[tid];
-            const int Re = s_ve[tid];
+            const double Rm = Rv;
             if (wide) {
                 const bool pos = tid < len && Rm > 0.0 && Rm <= 1.7976931348623157e308;
                 eref = wave_max(pos ? (double)(Re + ilogb(pos ? Rm : 1.0)) : -INFINITY);
@@ -687,11 +690,17 @@ __global__ __launch_bounds__(kThreads) void fin_pass(PassArgs A) {
             }
         }
     }
-    // arrival: the last block decides
-    wait_stores();
-    __syncthreads();
+    // arrival: the last block decides (an ASPOT pass stored from wave 0
+    // only: that wave's own wait orders its stores before the arrival)
     const int total = (rows_pass ? A.nrb : 0) + (PHASE != PH_SK_ROW ? A.ncb : 0);
-    if (tid == 0) s_last = (atomicAdd(&A.ws.glob[0], 1) == total - 1);
+    if (skp) {
+        wait_stores();
+        __syncthreads();
+    }
+    if (tid < kFinBlock) {
+        wait_stores();
+        if (tid == 0) s_last = (atomicAdd(&A.ws.glob[0], 1) == total - 1);
+    }
     __syncthreads();
     if (s_last) {
         decide(A, s_ctl, s_red, wide);
