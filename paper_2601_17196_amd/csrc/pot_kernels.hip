@@ -1162,8 +1162,8 @@ __global__ __launch_bounds__(1024) void result_kernel(PassArgs A, int algo, pot_
 // the R5 pass, the barycentre sums sum_i (Xbar 1)_i x_i and sum_j
 // (Xbar^T 1)_j y_j (row and column sums of Xbar from its factors) and the
 // mass: mom[0..8], mom[9..11], mom[12..14], mom[15].
-__global__ __launch_bounds__(1024) void moments_kernel(PassArgs A, double* mom) {
-    __shared__ double s_red[16 * 21];
+__global__ __launch_bounds__(256) void moments_kernel(PassArgs A, double* mom) {
+    __shared__ double s_red[4 * 21];
     const Ctl& c = *A.ws.ctl;
     const Ws& w = A.ws;
     const int tid = threadIdx.x, d = A.d;
@@ -1203,7 +1203,7 @@ __global__ __launch_bounds__(1024) void moments_kernel(PassArgs A, double* mom) 
             v[18 + a] += col * yj[a];
         }
     }
-    block_sum<21, 16>(v, s_red);
+    block_sum<21, 4>(v, s_red);
     if (tid == 0) {
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) mom[3 * a + b] = c.kappa * v[3 * a + b] + c.lambda * v[9 + a] * v[15 + b];
@@ -1307,7 +1307,7 @@ hipError_t launch_finish(const PassArgs& A, int algo, double* f, double* g, doub
 }
 
 hipError_t launch_moments(const PassArgs& A, double* mom, hipStream_t st) {
-    moments_kernel<<<1, 1024, 0, st>>>(A, mom);
+    moments_kernel<<<1, 256, 0, st>>>(A, mom);
     return hipGetLastError();
 }
 
