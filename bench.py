@@ -518,7 +518,8 @@ def bench_shared(pot, dev, eps, n=4096, B=256):
             "iters_max": int(max(its)), "iters_median": float(np.median(its)), "gemm_us": gms * 1e3,
             "gemm_shape": [rows, cols, depth],
             "roofline": {"bound": "mfma", "achieved": round(ach, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None},
+                         "frac": round(ach / BF16_MFMA_PEAK_TFLOPS, 4),
+                         "traffic": measured_traffic(f"shared_gemm_{n}x{B}_traffic.json")},
             "gemm_hbm_GB_per_s": (rows * depth * 2 + cols * depth * 2 + cols * rows * 4) / (gms * 1e-3) / 1e9}
 
 

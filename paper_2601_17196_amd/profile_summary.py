@@ -29,6 +29,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/pot_kernels.hip", "csrc/pot_device.h", "csrc/pot_internal.h"]
 BATCHED_SOURCES = ["csrc/pot_batched.hip", "csrc/pot_device.h", "csrc/pot_internal.h"]
+SHARED_SOURCES = ["csrc/pot_shared.hip", "csrc/pot_device.h", "csrc/pot_internal.h"]
 
 
 def kernel_source_hash(files=None) -> str:
@@ -52,7 +53,7 @@ def stats_table(path, title, command):
     return "\n".join(out) + "\n"
 
 
-def trace_section(path, pattern, min_frac):
+def trace_section(path, pattern, min_frac, note="the others are short autotuning launches"):
     """Durations (us) of the dispatches of the kernel matching pattern that
     take at least min_frac of its longest one."""
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
@@ -62,8 +63,9 @@ def trace_section(path, pattern, min_frac):
     top = max(durs)
     keep = [d for d in durs if d >= min_frac * top]
     out = ["", f"Dispatches of `{pattern}` taking at least {min_frac:g} of the longest ({len(keep)} of {len(durs)};"
-                f" the others are short autotuning launches):", ""]
-    out.append("    " + ", ".join(f"{d / 1e3:.2f} ms" if d >= 1e4 else f"{d:.2f} us" for d in keep))
+                f" {note}):", ""]
+    shown = ", ".join(f"{d / 1e3:.2f} ms" if d >= 1e4 else f"{d:.2f} us" for d in keep[:40])
+    out.append("    " + shown + (f", ... ({len(keep) - 40} more)" if len(keep) > 40 else ""))
     avg = sum(keep) / len(keep)
     out += ["", f"Average of these: {avg / 1e3:.3f} ms" if avg >= 1e4 else f"Average of these: {avg:.2f} us"]
     return "\n".join(out) + "\n"
@@ -138,6 +140,8 @@ def main():
     s.add_argument("--trace", help="kernel-trace CSV of the same run")
     s.add_argument("--kernel", help="kernel name pattern for the per-dispatch list")
     s.add_argument("--min-frac", type=float, default=0.5)
+    s.add_argument("--note", default="the others are short autotuning launches",
+                   help="what the shorter dispatches are")
     p = sub.add_parser("pmc")
     p.add_argument("fetch_csv")
     p.add_argument("write_csv")
@@ -147,17 +151,18 @@ def main():
     p.add_argument("--command", required=True)
     p.add_argument("--out", required=True)
     p.add_argument("--batched", action="store_true", help="the kernel is the batched one (its own sources)")
+    p.add_argument("--shared", action="store_true", help="the kernel is the shared-cost product (its own sources)")
     p.add_argument("--min-frac", type=float, default=0.0,
                    help="keep the kernel's dispatches of at least this fraction of its largest")
     a = ap.parse_args()
     if a.mode == "stats":
         text = stats_table(a.csv, a.title, a.command)
         if a.trace and a.kernel:
-            text += trace_section(a.trace, a.kernel, a.min_frac)
+            text += trace_section(a.trace, a.kernel, a.min_frac, a.note)
         open(a.out, "w").write(text)
     else:
         res = pmc_summary(a.fetch_csv, a.write_csv, a.copy_bytes, a.copy_pattern, a.kernel_pattern, a.command,
-                          BATCHED_SOURCES if a.batched else None, a.min_frac)
+                          BATCHED_SOURCES if a.batched else SHARED_SOURCES if a.shared else None, a.min_frac)
         json.dump(res, open(a.out, "w"), indent=1)
     print(open(a.out).read())
 
