@@ -127,10 +127,17 @@ typedef struct {
     int32_t* trace_i;      /* (device) per-iteration decisions, 3 ints each, or NULL */
     double* trace_d;       /* (device) per-iteration values {E, phi(z-check^t), phi(z-hat^t), theta_t}, or NULL */
     int32_t trace_cap;     /* iterations the trace buffers hold */
-    int32_t tile_rows;     /* rows per tile of the statistics pass (0: chosen from the grid size) */
+    int32_t tile_rows;     /* rows per tile of the statistics pass, 4..256 (0: chosen from the grid
+                              size; -1: tuned: 64, 128 and 256 are timed on the problem's start pass
+                              the first time an architecture, cost kind and shape bucket (n and m
+                              to the nearest power of two) is solved synchronously, and the fastest
+                              is kept; an asynchronous solve takes a kept result or the default).
+                              Tuning results are kept in memory and, when the environment variable
+                              POT_TUNE_CACHE names a file, in that JSON file across processes */
     int32_t member_elems;  /* pot_solve_batched: an instance with more than this many cost entries is
                               split by rows over a group of workgroups, each sweeping at most this
-                              many (0: autotuned on the batch, cached per batch shape) */
+                              many (0: autotuned on the batch, kept per architecture and batch shape
+                              with the tuning results) */
     int32_t gamma_rule;    /* 0: gamma and tol as above.  1 (algo Sinkhorn only): the tuned rule of
                               Algorithm 3 (Theorem 2), gamma = (2 eps / (49 H_min))^(1/p) and
                               tol = H_min gamma^p with H_min = min(H(r), H(c)),

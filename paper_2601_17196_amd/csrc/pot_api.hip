@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <string>
@@ -77,6 +79,137 @@ static Geometry geometry(const pot_problem* p, const pot_options* o) {
     return g;
 }
 
+// Tile heights the tuner tries (tile_rows = -1).
+static const int kTileCand[] = {64, 128, 256};
+
+static Geometry geometry_rows(const pot_problem* p, int br) {
+    pot_options o;
+    std::memset(&o, 0, sizeof(o));
+    o.tile_rows = br;
+    return geometry(p, &o);
+}
+
+// Workspace bytes of a solve (tile_rows = -1: enough for every candidate height).
+static size_t layout(const pot_problem* p, const Geometry& g, char* base, Ws* w);
+static size_t workspace_bytes(const pot_problem* p, const pot_options* o) {
+    size_t need = layout(p, geometry(p, o), nullptr, nullptr);
+    if (o && o->tile_rows == -1)
+        for (int br : kTileCand) need = std::max(need, layout(p, geometry_rows(p, br), nullptr, nullptr));
+    return need;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning results, kept in memory and, when the environment variable
+// POT_TUNE_CACHE names a file, in that file: one JSON object whose keys name
+// the device architecture, the tuned launch, the cost kind and the shape
+// bucket, and whose values are arrays of integers.  The file is read when a
+// lookup misses in memory and rewritten (merged with what it holds, through a
+// temporary file and a rename) after each new entry; a file that does not
+// parse is ignored.
+// ---------------------------------------------------------------------------
+typedef std::map<std::string, std::vector<long long>> TuneMap;
+static std::mutex g_tc_mu;
+static TuneMap g_tc;
+
+static bool tc_parse(const std::string& t, TuneMap& out) {
+    size_t i = 0;
+    auto ws = [&]() { while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\r' || t[i] == '\t')) ++i; };
+    auto eat = [&](char c) { ws(); if (i < t.size() && t[i] == c) { ++i; return true; } return false; };
+    if (!eat('{')) return false;
+    if (eat('}')) return true;
+    for (;;) {
+        if (!eat('"')) return false;
+        const size_t k0 = i;
+        while (i < t.size() && t[i] != '"' && t[i] != '\\') ++i;
+        if (i >= t.size() || t[i] != '"') return false;
+        const std::string key = t.substr(k0, i - k0);
+        ++i;
+        if (!eat(':') || !eat('[')) return false;
+        std::vector<long long> v;
+        if (!eat(']')) {
+            for (;;) {
+                ws();
+                char* end = nullptr;
+                const long long x = std::strtoll(t.c_str() + i, &end, 10);
+                if (end == t.c_str() + i) return false;
+                i = end - t.c_str();
+                v.push_back(x);
+                if (eat(']')) break;
+                if (!eat(',')) return false;
+            }
+        }
+        out[key] = v;
+        if (eat('}')) return true;
+        if (!eat(',')) return false;
+    }
+}
+
+static bool tc_read_file(const char* path, TuneMap& out) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return false;
+    std::string text((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    TuneMap m;
+    if (!tc_parse(text, m)) return false;
+    for (auto& kv : m) out[kv.first] = kv.second;
+    return true;
+}
+
+static std::string tc_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static bool tc_lookup(const std::string& key, std::vector<long long>& v) {
+    std::lock_guard<std::mutex> lk(g_tc_mu);
+    auto it = g_tc.find(key);
+    if (it == g_tc.end()) {
+        const char* path = std::getenv("POT_TUNE_CACHE");
+        if (!path || !*path) return false;
+        tc_read_file(path, g_tc);
+        it = g_tc.find(key);
+        if (it == g_tc.end()) return false;
+    }
+    v = it->second;
+    return true;
+}
+
+static void tc_store(const std::string& key, const std::vector<long long>& v) {
+    std::lock_guard<std::mutex> lk(g_tc_mu);
+    g_tc[key] = v;
+    const char* path = std::getenv("POT_TUNE_CACHE");
+    if (!path || !*path) return;
+    TuneMap all;
+    tc_read_file(path, all);                 // entries other processes wrote meanwhile
+    for (auto& kv : g_tc) all[kv.first] = kv.second;
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::binary | std::ios::trunc);
+        if (!f) return;
+        f << "{";
+        bool first = true;
+        for (auto& kv : all) {
+            f << (first ? "\n" : ",\n") << "  \"" << kv.first << "\": [";
+            for (size_t k = 0; k < kv.second.size(); ++k) f << (k ? ", " : "") << kv.second[k];
+            f << "]";
+            first = false;
+        }
+        f << "\n}\n";
+        if (!f) return;
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+// shape bucket of a dimension: the power of two nearest to it (in log scale)
+static int tc_bucket(int x) {
+    int b = 1;
+    while ((int64_t)b * 2 <= x) b *= 2;
+    return ((int64_t)x * x >= (int64_t)b * b * 2) ? 2 * b : b;
+}
+
 // Workspace layout; returns total bytes and fills ws if base != nullptr.
 static size_t layout(const pot_problem* p, const Geometry& g, char* base, Ws* ws) {
     const int64_t n = p->n, m = p->m;
@@ -142,7 +275,7 @@ static pot_status check_problem(const pot_problem* p, const pot_options* o) {
     if (o->step_rule < 0 || o->step_rule > 1) return fail(POT_ERR_INVALID_ARG, "step_rule");
     if (o->force_len < 0 || (o->force_len > 0 && !o->force)) return fail(POT_ERR_INVALID_ARG, "force");
     if (o->trace_cap < 0) return fail(POT_ERR_INVALID_ARG, "trace_cap");
-    if (o->tile_rows < 0 || o->tile_rows > 256) return fail(POT_ERR_INVALID_ARG, "tile_rows in [0, 256]");
+    if (o->tile_rows < -1 || o->tile_rows > 256) return fail(POT_ERR_INVALID_ARG, "tile_rows in [-1, 256]");
     if (!std::isfinite(o->w0)) return fail(POT_ERR_INVALID_ARG, "w0 not finite");
     return POT_OK;
 }
@@ -239,6 +372,92 @@ static hipError_t chunk_graph(const PassArgs& A, int algo, int chunk, hipGraphEx
     return hipSuccess;
 }
 
+// Median durations (ms) of the statistics pass at the start point (opts'
+// u0, v0, w0) with tile geometry g, over `reps` launches after 3 untimed
+// ones: the tile kernel in *avg_ms, the finalising kernel in *fin_ms (the
+// host waits for the launches).  prob->cmax (and cost_scale) must be set.
+static pot_status time_tile(const pot_problem* prob, const pot_options* opts, const Geometry& g, void* ws, int reps,
+                            double* avg_ms, double* fin_ms, hipStream_t st) {
+    Ws w;
+    layout(prob, g, (char*)ws, &w);
+    SetupArgs S{};
+    S.n = prob->n; S.m = prob->m; S.algo = POT_ASPOT; S.nx = g.nx; S.ny = g.ny;
+    S.gamma_rule = opts->gamma_rule; S.p = opts->p;
+    S.s = prob->s; S.eps = opts->eps; S.gamma_user = opts->gamma; S.tol_user = opts->tol;
+    S.A_user = opts->A; S.cmax = prob->cmax;
+    S.cost_scale = prob->kind == POT_COST_SQEUCLID_POINTS ? prob->cost_scale : 1.0;
+    S.w0 = opts->w0; S.r = prob->r; S.c = prob->c; S.ws = w;
+    HIPCHK(launch_setup(S, st));
+    PassArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.C = prob->C; A.ldc = prob->ldc; A.x = prob->x; A.y = prob->y; A.r = prob->r; A.c = prob->c;
+    A.n = prob->n; A.m = prob->m; A.d = prob->d; A.kind = prob->kind;
+    A.br = g.br; A.bc = g.bc; A.nx = g.nx; A.ny = g.ny;
+    A.nrb = (prob->n + 63) / 64; A.ncb = (prob->m + 63) / 64;
+    A.max_iter = 1; A.u0 = opts->u0; A.v0 = opts->v0; A.w0 = opts->w0;
+    A.ws = w;
+    A.phase = PH_INIT;
+    // 3 untimed launches, then `reps` timed ones; the medians are reported
+    for (int k = 0; k < 3; ++k) HIPCHK(launch_stats(A, st));
+    std::vector<hipEvent_t> ev(4 * (size_t)reps);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (int k = 0; k < reps; ++k)
+        HIPCHK(launch_stats_timed(A, st, ev[4 * k], ev[4 * k + 1], ev[4 * k + 2], ev[4 * k + 3]));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> t1(reps), t2(reps);
+    for (int k = 0; k < reps; ++k) {
+        float ms = 0.f, ms2 = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[4 * k], ev[4 * k + 1]));
+        HIPCHK(hipEventElapsedTime(&ms2, ev[4 * k + 2], ev[4 * k + 3]));
+        t1[k] = ms;
+        t2[k] = ms2;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    auto median = [](std::vector<double>& v) {
+        std::sort(v.begin(), v.end());
+        const size_t h = v.size() / 2;
+        return v.size() % 2 ? v[h] : 0.5 * (v[h - 1] + v[h]);
+    };
+    Ctl hc;
+    HIPCHK(hipMemcpy(&hc, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    if (hc.valid != 0) return fail(POT_ERR_INVALID_ARG, "invalid problem");
+    if (hc.status != POT_OK) return fail((pot_status)hc.status, "pass reported a non-finite sum");
+    *avg_ms = median(t1);
+    if (fin_ms) *fin_ms = median(t2);
+    return POT_OK;
+}
+
+// Tile height for tile_rows = -1: from the tuning results when this
+// architecture, cost kind and shape bucket have been tuned; otherwise, in a
+// synchronous solve, each of kTileCand is timed on the problem's start pass
+// (3 launches each, in the caller's workspace, which pot_workspace_bytes
+// sizes for every candidate) and the fastest is kept; an asynchronous solve
+// does not time (it takes the default height).
+static Geometry tuned_geometry(const pot_problem* p, const pot_options* o, void* ws, bool async, hipStream_t st) {
+    const Geometry dflt = geometry(p, o);
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s/tile/kind%d/n%d/m%d", tc_arch().c_str(), p->kind, tc_bucket(p->n),
+                  tc_bucket(p->m));
+    std::vector<long long> v;
+    if (tc_lookup(key, v) && v.size() == 1 && v[0] >= 4 && v[0] <= 256) return geometry_rows(p, (int)v[0]);
+    if (async) return dflt;
+    pot_problem q = *p;                                   // (timing only: any scale will do)
+    if (!(q.cmax > 0.0)) q.cmax = 1.0;
+    if (q.kind == POT_COST_SQEUCLID_POINTS && !(q.cost_scale > 0.0)) q.cost_scale = 1.0;
+    int best = dflt.br;
+    double best_ms = 1e300;
+    for (int br : kTileCand) {
+        double ms = 0.0;
+        if (time_tile(&q, o, geometry_rows(p, br), ws, 3, &ms, nullptr, st) != POT_OK) return dflt;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = br;
+        }
+    }
+    tc_store(key, {best});
+    return geometry_rows(p, best);
+}
+
 // Largest max_iter of an asynchronous solve (every iteration is enqueued).
 constexpr int kAsyncMaxIter = 1 << 20;
 
@@ -264,10 +483,10 @@ static pot_status solve_one(const pot_problem* p, const pot_options* o, void* ws
     }
     if (out && out->moments && p->kind != POT_COST_SQEUCLID_POINTS)
         return fail(POT_ERR_INVALID_ARG, "plan moments need the points cost");
-    const Geometry g = geometry(p, o);
-    const size_t need = layout(p, g, nullptr, nullptr);
-    if (!wsp || ws_bytes < need) return fail(POT_ERR_WORKSPACE, "workspace too small");
+    if (!wsp || ws_bytes < workspace_bytes(p, o)) return fail(POT_ERR_WORKSPACE, "workspace too small");
     if (((uintptr_t)wsp) & 255) return fail(POT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const Geometry g = o->tile_rows == -1 ? tuned_geometry(p, o, wsp, async, st) : geometry(p, o);
+    const size_t need = layout(p, g, nullptr, nullptr);
     char* base = (char*)wsp;
     Ws w;
     layout(p, g, base, &w);
@@ -1037,13 +1256,11 @@ static hipError_t run_batched(const BArgs& B, int kind, int grid, bool use_graph
 
 // Autotuner of the batched launch: the group share of cost entries per
 // member and the workgroups per CU, timed on the batch itself (3 iterations,
-// no rounding) and cached per batch shape.
+// no rounding) and kept with the tuning results per batch shape.
 struct BTune {
     int64_t share;
     int per_cu;
 };
-static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int64_t, int64_t, int>, BTune> g_tune;
 
 static pot_status solve_batched(int32_t batch, const pot_problem* probs, const pot_options* o, const pot_warm* warm,
                                 void* wsp, size_t ws_bytes, pot_result* res, const pot_batch_outputs* out,
@@ -1159,13 +1376,14 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
 
     BTune tune{o->member_elems > 0 ? (int64_t)o->member_elems : 0, std::min(2, max_per_cu)};
     if (tune.share == 0) {
-        const auto key = std::make_tuple(kind, batch, total >> 16, largest, o->algo);
-        bool have = false;
-        {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto it = g_tune.find(key);
-            if (it != g_tune.end()) { tune = it->second; have = true; }
-        }
+        // tuning results keyed by architecture, CU count, cost kind, algorithm and batch shape
+        char key[200];
+        std::snprintf(key, sizeof(key), "%s/batched/cus%d/kind%d/algo%d/b%d/e%lld/l%lld", tc_arch().c_str(), cus,
+                      kind, o->algo, batch, (long long)(total >> 16), (long long)largest);
+        std::vector<long long> cached;
+        const bool have = tc_lookup(key, cached) && cached.size() == 2 && cached[0] > 0 && cached[1] >= 1 &&
+                          cached[1] <= max_per_cu;
+        if (have) tune = BTune{(int64_t)cached[0], (int)cached[1]};
         if (!have) {
             // time each candidate on 3 iterations of the batch (no rounding, no outputs)
             hipEvent_t e0, e1;
@@ -1195,8 +1413,7 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             tune = bt;
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune[key] = tune;
+            tc_store(key, {(long long)tune.share, (long long)tune.per_cu});
         }
     }
     HIPCHK(upload(tune.share));
@@ -1217,8 +1434,7 @@ size_t pot_workspace_bytes(const pot_problem* prob, const pot_options* opts) {
     if (!prob || prob->n < 1 || prob->m < 1) return 0;
     pot_options dflt;
     std::memset(&dflt, 0, sizeof(dflt));
-    const Geometry g = geometry(prob, opts ? opts : &dflt);
-    return layout(prob, g, nullptr, nullptr);
+    return workspace_bytes(prob, opts ? opts : &dflt);
 }
 
 pot_status pot_solve(const pot_problem* prob, const pot_options* opts, void* ws, size_t ws_bytes,
@@ -1346,59 +1562,12 @@ pot_status pot_time_pass(const pot_problem* prob, const pot_options* opts, void*
         if (reps < 1 || !avg_ms) return fail(POT_ERR_INVALID_ARG, "reps >= 1 and avg_ms required");
         pot_status cs = check_problem(prob, opts);
         if (cs != POT_OK) return cs;
-        hipStream_t st = (hipStream_t)stream;
         const Geometry g = geometry(prob, opts);
         const size_t need = layout(prob, g, nullptr, nullptr);
         if (!ws || ws_bytes < need || (((uintptr_t)ws) & 255)) return fail(POT_ERR_WORKSPACE, "workspace");
         if (prob->cmax <= 0.0 || (prob->kind == POT_COST_SQEUCLID_POINTS && prob->cost_scale <= 0.0))
             return fail(POT_ERR_INVALID_ARG, "pot_time_pass needs cmax (and cost_scale) given");
-        Ws w;
-        layout(prob, g, (char*)ws, &w);
-        SetupArgs S{};
-        S.n = prob->n; S.m = prob->m; S.algo = POT_ASPOT; S.nx = g.nx; S.ny = g.ny;
-        S.gamma_rule = opts->gamma_rule; S.p = opts->p;
-        S.s = prob->s; S.eps = opts->eps; S.gamma_user = opts->gamma; S.tol_user = opts->tol;
-        S.A_user = opts->A; S.cmax = prob->cmax;
-        S.cost_scale = prob->kind == POT_COST_SQEUCLID_POINTS ? prob->cost_scale : 1.0;
-        S.w0 = opts->w0; S.r = prob->r; S.c = prob->c; S.ws = w;
-        HIPCHK(launch_setup(S, st));
-        PassArgs A;
-        std::memset(&A, 0, sizeof(A));
-        A.C = prob->C; A.ldc = prob->ldc; A.x = prob->x; A.y = prob->y; A.r = prob->r; A.c = prob->c;
-        A.n = prob->n; A.m = prob->m; A.d = prob->d; A.kind = prob->kind;
-        A.br = g.br; A.bc = g.bc; A.nx = g.nx; A.ny = g.ny;
-        A.nrb = (prob->n + 63) / 64; A.ncb = (prob->m + 63) / 64;
-        A.max_iter = 1; A.u0 = opts->u0; A.v0 = opts->v0; A.w0 = opts->w0;
-        A.ws = w;
-        A.phase = PH_INIT;
-        // 3 untimed launches, then `reps` timed ones; the medians are reported
-        for (int k = 0; k < 3; ++k) HIPCHK(launch_stats(A, st));
-        std::vector<hipEvent_t> ev(4 * (size_t)reps);
-        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-        for (int k = 0; k < reps; ++k)
-            HIPCHK(launch_stats_timed(A, st, ev[4 * k], ev[4 * k + 1], ev[4 * k + 2], ev[4 * k + 3]));
-        HIPCHK(hipStreamSynchronize(st));
-        std::vector<double> t1(reps), t2(reps);
-        for (int k = 0; k < reps; ++k) {
-            float ms = 0.f, ms2 = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev[4 * k], ev[4 * k + 1]));
-            HIPCHK(hipEventElapsedTime(&ms2, ev[4 * k + 2], ev[4 * k + 3]));
-            t1[k] = ms;
-            t2[k] = ms2;
-        }
-        for (auto& e : ev) (void)hipEventDestroy(e);
-        auto median = [](std::vector<double>& v) {
-            std::sort(v.begin(), v.end());
-            const size_t h = v.size() / 2;
-            return v.size() % 2 ? v[h] : 0.5 * (v[h - 1] + v[h]);
-        };
-        Ctl hc;
-        HIPCHK(hipMemcpy(&hc, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-        if (hc.valid != 0) return fail(POT_ERR_INVALID_ARG, "invalid problem");
-        if (hc.status != POT_OK) return fail((pot_status)hc.status, "pass reported a non-finite sum");
-        *avg_ms = median(t1);
-        if (fin_ms) *fin_ms = median(t2);
-        return POT_OK;
+        return time_tile(prob, opts, g, ws, reps, avg_ms, fin_ms, (hipStream_t)stream);
     } catch (...) {
         return fail(POT_ERR_DEVICE, "internal error");
     }
