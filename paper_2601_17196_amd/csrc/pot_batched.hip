@@ -168,23 +168,6 @@ __device__ __forceinline__ void unpack_chunk(const f32x4& q, float (&cv)[VW]) {
     }
 }
 
-// Row sums of a sweep step, reduced together.  Each lane holds a partial
-// sum of each of the step's U rows.  A swap of the upper and lower 32 lanes
-// between two rows' registers (swap32_add) and one add leave row a in lanes
-// 0-31 and row b in lanes 32-63, each lane summing two; a swap of odd and
-// even 16-lane groups between two such results (swap16_add) leaves one row
-// per 16-lane group, each lane summing four; four DPP steps then add the
-// group.  Every lane of group g ends with the total of one row:
-//   U >= 4: row 4h + ((g & 1) << 1 | g >> 1) in out[h];  U = 2: row g >> 1.
-// The order of the additions is fixed (bitwise reproducible).
-__device__ __forceinline__ double group16_sum(double v) {
-    v += dpp_d<kQuadX1>(v, 0.0);
-    v += dpp_d<kQuadX2>(v, 0.0);
-    v += dpp_d<kHalfMirror>(v, 0.0);
-    v += dpp_d<kMirror>(v, 0.0);
-    return v;
-}
-
 // Sixteen values summed over the 64 lanes of a wave, all together: the two
 // lane swaps above halve the values each lane carries twice (16 -> 8 -> 4),
 // then two exchanges inside 16-lane rows (row_mirror, row_half_mirror: a lane
@@ -240,19 +223,6 @@ __device__ __forceinline__ void block_sum_rc(double (&Rs)[kScal], double (&Cs)[k
     }
 }
 
-template <int U>
-__device__ __forceinline__ void rows_reduce(const double (&rs)[U], double (&out)[(U + 3) / 4]) {
-    static_assert(U == 2 || U == 4 || U == 8, "rows per step");
-    if constexpr (U == 2) {
-        const double t = swap32_add(rs[0], rs[1]);
-        out[0] = group16_sum(swap16_add(t, t));
-    } else {
-#pragma unroll
-        for (int h = 0; h < U / 4; ++h)
-            out[h] = group16_sum(swap16_add(swap32_add(rs[4 * h], rs[4 * h + 1]),
-                                            swap32_add(rs[4 * h + 2], rs[4 * h + 3])));
-    }
-}
 
 // One sweep of the member's rows: row sums into S.R (relative to 2^K), column
 // partials into per-thread FP64 accumulators; returns the member's level (the
