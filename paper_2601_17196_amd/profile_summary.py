@@ -34,11 +34,15 @@ SHARED_SOURCES = ["csrc/pot_shared.hip", "csrc/pot_device.h", "csrc/pot_internal
 
 def kernel_source_hash(files=None) -> str:
     """Hash of the sources a kernel is built from (default: the
-    single-instance kernels)."""
+    single-instance kernels) and of the compiler flags of each HIP source."""
+    from . import build as hipbuild
     h = hashlib.sha256()
     for f in (files or KERNEL_SOURCES):
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
+        name = os.path.basename(f)
+        if name in hipbuild.SOURCES:
+            h.update(" ".join(hipbuild.HIPCC_FLAGS + hipbuild.SOURCE_FLAGS.get(name, [])).encode())
     return h.hexdigest()[:16]
 
 
