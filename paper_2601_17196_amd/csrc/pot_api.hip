@@ -14,6 +14,8 @@
 #include <tuple>
 #include <vector>
 
+#include <unistd.h>
+
 #include "pot_internal.h"
 
 namespace pot {
@@ -185,7 +187,7 @@ static void tc_store(const std::string& key, const std::vector<long long>& v) {
     TuneMap all;
     tc_read_file(path, all);                 // entries other processes wrote meanwhile
     for (auto& kv : g_tc) all[kv.first] = kv.second;
-    const std::string tmp = std::string(path) + ".tmp";
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long long)getpid());   // (one per process)
     {
         std::ofstream f(tmp, std::ios::binary | std::ios::trunc);
         if (!f) return;
@@ -198,9 +200,13 @@ static void tc_store(const std::string& key, const std::vector<long long>& v) {
             first = false;
         }
         f << "\n}\n";
-        if (!f) return;
+        if (!f) {
+            f.close();
+            std::remove(tmp.c_str());
+            return;
+        }
     }
-    std::rename(tmp.c_str(), path);
+    if (std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
 }
 
 // shape bucket of a dimension: the power of two nearest to it (in log scale)
@@ -439,7 +445,10 @@ static Geometry tuned_geometry(const pot_problem* p, const pot_options* o, void*
     std::snprintf(key, sizeof(key), "%s/tile/kind%d/n%d/m%d", tc_arch().c_str(), p->kind, tc_bucket(p->n),
                   tc_bucket(p->m));
     std::vector<long long> v;
-    if (tc_lookup(key, v) && v.size() == 1 && v[0] >= 4 && v[0] <= 256) return geometry_rows(p, (int)v[0]);
+    // (a recorded height is taken only if it is a candidate: the workspace is
+    // sized for the candidates)
+    if (tc_lookup(key, v) && v.size() == 1 && std::count(std::begin(kTileCand), std::end(kTileCand), v[0]) == 1)
+        return geometry_rows(p, (int)v[0]);
     if (async) return dflt;
     pot_problem q = *p;                                   // (timing only: any scale will do)
     if (!(q.cmax > 0.0)) q.cmax = 1.0;

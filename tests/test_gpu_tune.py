@@ -81,3 +81,22 @@ def test_unparsable_cache_ignored(tmp_path, monkeypatch):
     cache = _read(path)
     assert any("/tile/kind0/n256/m256" in k for k in cache)
     check_definition1(inst, "f32", "aspot", out, lp_key=None)
+
+
+def test_recorded_height_outside_candidates_ignored(tmp_path, monkeypatch):
+    """A recorded tile height that is not one of the tuned candidates (the
+    workspace is sized for the candidates) is not used: the solve tunes
+    again and records a candidate in its place."""
+    import torch
+    path = tmp_path / "tune.json"
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = f"{arch}/tile/kind0/n1024/m1024"     # (a bucket no other test tunes: results stay in memory)
+    path.write_text(json.dumps({key: [16]}))
+    monkeypatch.setenv("POT_TUNE_CACHE", str(path))
+    inst = I.uniform_pair(1100, 1000, 2, 4401, mass_r=1.0, mass_c=1.1, s_frac=0.8)
+    print("tile tuning over a recorded height outside the candidates", flush=True)
+    out = gpu_solve(inst, "f32", "aspot", tile_rows=-1)
+    assert out.status == 0
+    cache = _read(path)
+    assert cache[key][0] in (64, 128, 256), cache
+    check_definition1(inst, "f32", "aspot", out, lp_key=None)
