@@ -20,8 +20,6 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include <type_traits>
-
 #include "pot_device.h"
 
 namespace pot {
@@ -263,10 +261,9 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
                 }
             }
         };
-        // one step of U rows; MASK: a row or a column of the step lies outside
-        // the member (its terms are zeroed)
-        auto step = [&](int s, auto mask_tag) __attribute__((always_inline)) {
-            constexpr bool MASK = decltype(mask_tag)::value;
+        fetch(0, cur);
+        for (int s = 0; s * U < nq; ++s) {
+            if ((s + 1) * U < nq) fetch(s + 1, nxt);
             double rsum[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) rsum[u] = 0.0;
@@ -291,7 +288,7 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
                             ex = __builtin_amdgcn_exp2f(fmaf(cv[e], -(float)G2, (float)ar + (float)b[k][e]));
                         else
                             ex = exp2_split(fma((double)cv[e], -G2, ar + b[k][e]));
-                        if constexpr (MASK) ex = (rv && j < m) ? ex : 0.0f;
+                        ex = (rv && j < m) ? ex : 0.0f;
                         rs += ex;
                         col32[e] += ex;
                     }
@@ -314,13 +311,6 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
                     }
                 }
             }
-        };
-        const bool full_cols = KC * CW <= m;
-        fetch(0, cur);
-        for (int s = 0; s * U < nq; ++s) {
-            if ((s + 1) * U < nq) fetch(s + 1, nxt);
-            if (full_cols && (s + 1) * U <= nq) step(s, std::false_type{});
-            else step(s, std::true_type{});
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
