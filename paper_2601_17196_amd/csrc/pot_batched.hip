@@ -248,16 +248,30 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
         for (int e = 0; e < VW; ++e) colacc[k][e] = 0.0;
     if (nq > 0) {
         f32x4 cur[U][KC], nxt[U][KC];
+        // The loads of step s.  With aligned rows every load is one 16-byte
+        // load: a lane past the row's end reads the last group inside the
+        // row's stride (its terms are masked).  The choice is made once per
+        // step, not per row: the register writes of a per-row partial path
+        // would hold each row's load until the previous loads returned.
+        const int jlast = (int)M.A.ldc - VW;
         auto fetch = [&](int s, f32x4 (&buf)[U][KC]) __attribute__((always_inline)) {
+            if (vec) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int q = min(s * U + u, nq - 1);
-                const char* rowp = Cb + (int64_t)(M.r0 + wave + kBWaves * q) * rstride;
+                for (int u = 0; u < U; ++u) {
+                    const int q = min(s * U + u, nq - 1);
+                    const char* rowp = Cb + (int64_t)(M.r0 + wave + kBWaves * q) * rstride;
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    const int jb = min(k * CW + lane * VW, m - 1);
-                    const bool full = vec && (k + 1) * CW <= m;
-                    buf[u][k] = load_chunk<KIND, VW>(rowp, jb, m, full);
+                    for (int k = 0; k < KC; ++k)
+                        buf[u][k] = *(const f32x4*)(rowp + (int64_t)min(k * CW + lane * VW, jlast) * EB);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = min(s * U + u, nq - 1);
+                    const char* rowp = Cb + (int64_t)(M.r0 + wave + kBWaves * q) * rstride;
+#pragma unroll
+                    for (int k = 0; k < KC; ++k)
+                        buf[u][k] = load_chunk<KIND, VW>(rowp, min(k * CW + lane * VW, m - 1), m, false);
                 }
             }
         };
