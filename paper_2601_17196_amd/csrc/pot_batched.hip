@@ -358,18 +358,21 @@ __device__ bool member_pass(Member& M, BShared& S) {
     // ---- the point of the pass, clamped as in the tile kernel
     constexpr double kClamp = 536870912.0;  // 2^29
     const double wp = w_point<PH>(A, c);
-    for (int r = tid; r < nr; r += kBThreads) {
-        const int i = r0 + r;
-        const Cand q = load_cand<PH>(A, RV, 0, i);
-        const double x = eval_point<PH>(A, c, RV, q, 0, i, true);
-        S.xr[r] = x;
-        S.a[r] = fmin(fmax((x + wp) * kLog2e, -kClamp), kClamp);
-    }
-    for (int j = tid; j < m; j += kBThreads) {
-        const Cand q = load_cand<PH>(A, CV, 1, j);
-        const double x = eval_point<PH>(A, c, CV, q, 1, j, true);
-        S.xc[j] = x;
-        S.b[j] = fmin(fmax(x * kLog2e, -kClamp), kClamp);
+    // (rows and columns side by side: one round trip for the duals' loads)
+    for (int k = tid; k < nr + m; k += kBThreads) {
+        if (k < nr) {
+            const int i = r0 + k;
+            const Cand q = load_cand<PH>(A, RV, 0, i);
+            const double x = eval_point<PH>(A, c, RV, q, 0, i, true);
+            S.xr[k] = x;
+            S.a[k] = fmin(fmax((x + wp) * kLog2e, -kClamp), kClamp);
+        } else {
+            const int j = k - nr;
+            const Cand q = load_cand<PH>(A, CV, 1, j);
+            const double x = eval_point<PH>(A, c, CV, q, 1, j, true);
+            S.xc[j] = x;
+            S.b[j] = fmin(fmax(x * kLog2e, -kClamp), kClamp);
+        }
     }
     __syncthreads();
 
