@@ -210,7 +210,9 @@ __device__ __forceinline__ void block_sum_rc(double (&Rs)[kScal], double (&Cs)[k
     const double z = wave_sum16(v);
     const int q = lane >> 2;
     const int idx = ((q & 1) << 3) | ((q & 2) << 1) | ((q & 4) >> 1) | ((q & 8) >> 3);
-    double* red = &S.colw[0][0];
+    // (in the column offsets' area: the pass does not read them again, while
+    // the column partials may still be read by a slower wave's steps)
+    double* red = &S.b[0];
     if ((lane & 3) == 0) red[wave * 16 + idx] = z;
     __syncthreads();
     if (wave == 0) {
@@ -425,26 +427,32 @@ __device__ bool member_pass(Member& M, BShared& S) {
     }
     __syncthreads();
     if (tid == 0) S.K = K;
-    if (PH == PH_INIT)
-        for (int r = tid; r < nr; r += kBThreads) S.lR[r] = log(S.R[r]) + (double)K * kLn2;
-    if (ROWS)
-        for (int r = tid; r < nr; r += kBThreads) S.R[r] *= scale_d;
-    if (COLS) {
-        for (int j = tid; j < m; j += kBThreads) {
-            const double q = colw_sum(S, j) * scale_d;
-            if (M.G == 1) S.Q[j] = q;
-            else st_agent(&M.colpart[(int64_t)M.mem * m + j], q);
-        }
-        if (M.G > 1) {
-            if (!group_sync(M, S)) return false;
+    // A lone member's ASPOT pass forms each row's and column's scaled sum in
+    // the thread that steps it (below); otherwise they are combined here,
+    // behind one more barrier.
+    const bool fused = ROWS && COLS && M.G == 1;
+    if (!fused) {
+        if (PH == PH_INIT)
+            for (int r = tid; r < nr; r += kBThreads) S.lR[r] = log(S.R[r]) + (double)K * kLn2;
+        if (ROWS)
+            for (int r = tid; r < nr; r += kBThreads) S.R[r] *= scale_d;
+        if (COLS) {
             for (int j = tid; j < m; j += kBThreads) {
-                double q = 0.0;
-                for (int g = 0; g < M.G; ++g) q += ld_agent(&M.colpart[(int64_t)g * m + j]);
-                S.Q[j] = q;
+                const double q = colw_sum(S, j) * scale_d;
+                if (M.G == 1) S.Q[j] = q;
+                else st_agent(&M.colpart[(int64_t)M.mem * m + j], q);
+            }
+            if (M.G > 1) {
+                if (!group_sync(M, S)) return false;
+                for (int j = tid; j < m; j += kBThreads) {
+                    double q = 0.0;
+                    for (int g = 0; g < M.G; ++g) q += ld_agent(&M.colpart[(int64_t)g * m + j]);
+                    S.Q[j] = q;
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- steps and the scalars of the decisions
     double Rs[kScal], Cs[kScal];
@@ -477,11 +485,17 @@ __device__ bool member_pass(Member& M, BShared& S) {
         for (int k = tid; k < nr + m; k += kBThreads) {
             if (k < nr) {
                 const StepPre p = {S.xr[k], S.rt[k], S.lrt[k], 0.0};
-                aspot_step<PH>(A, true, r0 + k, S.R[k], Ke, S.R[k], p, Rs);
+                double R = S.R[k];
+                if (fused) {
+                    if (PH == PH_INIT) S.lR[k] = log(R) + (double)K * kLn2;
+                    R *= scale_d;
+                }
+                aspot_step<PH>(A, true, r0 + k, R, Ke, R, p, Rs);
             } else {
                 const int j = k - nr;
                 const StepPre p = {S.xc[j], S.ct[j], S.lct[j], 0.0};
-                aspot_step<PH>(A, false, j, S.Q[j], Ke, 0.0, p, Cs);
+                const double Q = fused ? colw_sum(S, j) * scale_d : S.Q[j];
+                aspot_step<PH>(A, false, j, Q, Ke, 0.0, p, Cs);
             }
         }
         block_sum_rc(Rs, Cs, S);

@@ -87,6 +87,23 @@ def test_batched_uneven_matches_oracle(algo):
     assert same >= len(insts) // 2      # most runs take every decision the same way
 
 
+def test_batched_bitwise_reproducible():
+    """The same batch solved twice gives the same bits: iteration counts,
+    costs and log-scalings (every sum is taken in a fixed order, and no
+    workgroup reads shared memory that another may still be writing).
+    Instances with more rows and columns than threads step several per
+    thread, which is where a missed barrier would show."""
+    insts = _insts(SIZES, seed0=500)
+    st1, res1, fg1 = _solve(insts, "aspot")
+    st2, res2, fg2 = _solve(insts, "aspot")
+    assert st1 == 0 and st2 == 0
+    for inst, a, b, x, y in zip(insts, res1, res2, fg1, fg2):
+        assert a["iters"] == b["iters"], inst.name
+        assert a["cost"] == b["cost"], inst.name
+        for u, v in zip(x, y):
+            assert np.array_equal(u.cpu().numpy(), v.cpu().numpy()), inst.name
+
+
 @pytest.mark.parametrize("algo", ["aspot", "sinkhorn"])
 def test_batched_groups_split_rows(algo):
     """member_elems = 4096 splits every instance above 4096 entries over up to
