@@ -243,7 +243,8 @@ size_t pot_workspace_bytes_batched(int32_t batch, const pot_problem* probs, cons
 /* Solve `batch` independent instances in one persistent launch (a captured
  * HIP graph of two kernels unless POT_FLAG_NO_GRAPH).  Each instance is a
  * dense POT_COST_F32 or POT_COST_BF16 cost (the same kind for the whole
- * batch) with 1 <= n, m <= 1024; the algorithm, its defaults and the
+ * batch) with 1 <= n, m <= 1024 and a row stride (ldc times the element
+ * size) below 2^31 bytes; the algorithm, its defaults and the
  * rounding are those of pot_solve, per instance.  Workgroups take instances
  * from a device queue, largest first (ties: larger s first); an instance
  * with more than opts->member_elems cost entries is split by rows over a

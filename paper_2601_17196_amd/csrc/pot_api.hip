@@ -1295,6 +1295,8 @@ static pot_status solve_batched(int32_t batch, const pot_problem* probs, const p
             return fail(POT_ERR_INVALID_ARG, "batched instances need 1 <= n, m <= 1024");
         if (!p.C || !p.r || !p.c) return fail(POT_ERR_INVALID_ARG, "C, r and c are required");
         if (p.ldc < p.m) return fail(POT_ERR_INVALID_ARG, "ldc < m");
+        if (p.ldc * (kind == POT_COST_BF16 ? 2 : 4) >= ((int64_t)1 << 31))
+            return fail(POT_ERR_INVALID_ARG, "batched instances need a row stride below 2^31 bytes");
         if (!(p.s > 0.0) || !std::isfinite(p.s)) return fail(POT_ERR_INVALID_ARG, "s must be positive");
         if (!std::isfinite(p.cmax)) return fail(POT_ERR_INVALID_ARG, "cmax must be finite");
         total += (int64_t)p.n * p.m;

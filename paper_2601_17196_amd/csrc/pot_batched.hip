@@ -241,7 +241,7 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
     const int m = M.m;
     const bool vec = M.D->vec != 0;
     const char* Cb = (const char*)M.A.C;
-    const int64_t rstride = M.A.ldc * EB;
+    const uint32_t rstride = (uint32_t)(M.A.ldc * EB);     // (below 2^31: checked on the host)
     const int nq = (M.nr - wave + kBWaves - 1) / kBWaves;   // rows of this wave
     double lvl = 0.0;
 #pragma unroll
@@ -261,7 +261,7 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = min(s * U + u, nq - 1);
-                    const char* rowp = Cb + (int64_t)(M.r0 + wave + kBWaves * q) * rstride;
+                    const char* rowp = Cb + (uint64_t)(uint32_t)(M.r0 + wave + kBWaves * q) * rstride;
 #pragma unroll
                     for (int k = 0; k < KC; ++k)
                         buf[u][k] = *(const f32x4*)(rowp + (int64_t)min(k * CW + lane * VW, jlast) * EB);
@@ -270,32 +270,29 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = min(s * U + u, nq - 1);
-                    const char* rowp = Cb + (int64_t)(M.r0 + wave + kBWaves * q) * rstride;
+                    const char* rowp = Cb + (uint64_t)(uint32_t)(M.r0 + wave + kBWaves * q) * rstride;
 #pragma unroll
                     for (int k = 0; k < KC; ++k)
                         buf[u][k] = load_chunk<KIND, VW>(rowp, min(k * CW + lane * VW, m - 1), m, false);
                 }
             }
         };
-        fetch(0, cur);
-        for (int s = 0; s * U < nq; ++s) {
-            if ((s + 1) * U < nq) fetch(s + 1, nxt);
+        // one step of U rows from its loads
+        auto step = [&](int s, const f32x4 (&buf)[U][KC]) __attribute__((always_inline)) {
+            // (every sum starts from its first term: the terms are >= 0, so
+            // the results are those of sums started from zero)
             double rsum[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) rsum[u] = 0.0;
 #pragma unroll
             for (int k = 0; k < KC; ++k) {
                 float col32[VW];
-#pragma unroll
-                for (int e = 0; e < VW; ++e) col32[e] = 0.0f;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = s * U + u;
                     const bool rv = q < nq;
                     const double ar = S.a[wave + kBWaves * min(q, nq - 1)] - Kd;
                     float cv[VW];
-                    unpack_chunk<KIND, VW>(cur[u][k], cv);
-                    float rs = 0.0f;
+                    unpack_chunk<KIND, VW>(buf[u][k], cv);
+                    float rs;
 #pragma unroll
                     for (int e = 0; e < VW; ++e) {
                         const int j = k * CW + lane * VW + e;
@@ -304,11 +301,15 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
                             ex = __builtin_amdgcn_exp2f(fmaf(cv[e], -(float)G2, (float)ar + (float)b[k][e]));
                         else
                             ex = exp2_split(fma((double)cv[e], -G2, ar + b[k][e]));
+                        // (every term is computed, then masked: the empty
+                        // barrier keeps the mask from becoming a branch
+                        // around the term)
+                        asm volatile("" : "+v"(ex));
                         ex = (rv && j < m) ? ex : 0.0f;
-                        rs += ex;
-                        col32[e] += ex;
+                        rs = e == 0 ? ex : rs + ex;
+                        col32[e] = u == 0 ? ex : col32[e] + ex;
                     }
-                    rsum[u] += (double)rs;
+                    rsum[u] = k == 0 ? (double)rs : rsum[u] + (double)rs;
                 }
 #pragma unroll
                 for (int e = 0; e < VW; ++e) colacc[k][e] += (double)col32[e];
@@ -327,10 +328,15 @@ __device__ double member_sweep(const Member& M, BShared& S, double G2, double Kd
                     }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int k = 0; k < KC; ++k) cur[u][k] = nxt[u][k];
+        };
+        // two buffers in turn (no register copies)
+        fetch(0, cur);
+        for (int s = 0; s * U < nq; s += 2) {
+            if ((s + 1) * U < nq) fetch(s + 1, nxt);
+            step(s, cur);
+            if ((s + 1) * U >= nq) break;
+            if ((s + 2) * U < nq) fetch(s + 2, cur);
+            step(s + 1, nxt);
         }
     }
 #pragma unroll
