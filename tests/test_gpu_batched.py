@@ -192,6 +192,12 @@ def test_batched_rejects_unsupported():
     st, _, _ = pot.solve_batched(probs, insts[0].eps)
     assert st == pot.ERR_UNSUPPORTED
     assert "same cost kind" in pot.last_error()
+    # a row stride of 2^31 bytes or more is rejected before anything is read
+    probs = _dev(insts)
+    probs[0]["ldc"] = 1 << 29
+    st, _, _ = pot.solve_batched(probs, insts[0].eps)
+    assert st == pot.ERR_INVALID_ARG
+    assert "row stride" in pot.last_error()
 
 
 def test_batched_max_iter_still_feasible():
