@@ -18,7 +18,7 @@ solver options.
 
 Rooflines.  The headline's dominant kernel is the persistent batched kernel:
 its work is n m exponentials per statistics pass (three passes per ASPOT
-iteration), bound by the vector ALU (each 256-column C5 row costs about 14
+iteration), bound by the vector ALU (each 256-column C5 row costs about 13.75
 VALU instructions per element, the exponential at a quarter rate, which
 gives the peak BATCHED_PEAK_GELEM below at 256 CUs x 64 lanes x 2.4 GHz).
 The single-instance tile kernel streams C and is bound by HBM (8 TB/s).
@@ -44,10 +44,11 @@ HBM_PEAK_GBS = 8000.0
 # Vector-ALU ceilings in G elements/s: 256 CUs x 64 lanes x 2.4 GHz =
 # 3.93e13 lane-instructions/s, divided by the issue cost of one element of the
 # statistics pass in the compiled inner loops (the exponential counts 4: it
-# issues at a quarter rate).  Batched 256-column rows: 14.19 VALU incl. the
-# exponential -> 17.19; tile kernel, points cost (d = 3): 12.44 -> 15.44.
+# issues at a quarter rate).  Batched 256-column rows: 13.75 VALU incl. the
+# exponential (440 per 32-element step of the compiled sweep) -> 16.75; tile
+# kernel, points cost (d = 3): 12.44 -> 15.44.
 ALU_LANE_OPS = 256 * 64 * 2.4e9
-BATCHED_PEAK_GELEM = ALU_LANE_OPS / 17.19 / 1e9
+BATCHED_PEAK_GELEM = ALU_LANE_OPS / 16.75 / 1e9
 POINTS_PEAK_GELEM = ALU_LANE_OPS / 15.44 / 1e9
 COPY_BYTES = 256 << 20          # the plain copy of the counter-scale probe (bytes read, and written)
 PROFILES = os.path.join(ROOT, "profiles")
