@@ -104,6 +104,44 @@ def test_batched_bitwise_reproducible():
             assert np.array_equal(u.cpu().numpy(), v.cpu().numpy()), inst.name
 
 
+def test_batched_padded_rows_masked():
+    """Rows with a stride beyond m (aligned, so the sweep reads whole 16-byte
+    groups and a lane past the row's end reads the stride's padding): the
+    padding is filled with NaN and the results are bit for bit those of the
+    unpadded rows, for FP32 and BF16."""
+    import torch
+
+    from paper_2601_17196_amd import pot
+    insts = _insts([(70, 180), (33, 252), (129, 100), (40, 8)], seed0=900)
+    for kind in ("f32", "bf16"):
+        plain = _dev(insts, kind)
+        padded = []
+        for inst, pr in zip(insts, plain):
+            m = inst.m
+            ld = (m + 7) // 8 * 8 + 8
+            host = inst.C32 if kind == "f32" else I.to_bf16_bits(inst.C32).view(np.int16)
+            buf = np.empty((inst.n, ld), dtype=host.dtype)
+            if kind == "f32":
+                buf[:] = np.nan
+            else:
+                buf[:] = np.int16(0x7FC0)              # a BF16 NaN
+            buf[:, :m] = host
+            t = torch.from_numpy(buf).cuda()
+            q = dict(pr)
+            q["C"] = t
+            q["ldc"] = ld
+            padded.append(q)
+        print(f"batched padded rows ({kind})", flush=True)
+        st1, res1, fg1 = pot.solve_batched(plain, insts[0].eps, want_uv=True)
+        st2, res2, fg2 = pot.solve_batched(padded, insts[0].eps, want_uv=True)
+        torch.cuda.synchronize()
+        assert st1 == 0 and st2 == 0
+        for inst, a, b, x, y in zip(insts, res1, res2, fg1, fg2):
+            assert a["iters"] == b["iters"] and a["cost"] == b["cost"], (kind, inst.name)
+            for u, v in zip(x, y):
+                assert np.array_equal(u.cpu().numpy(), v.cpu().numpy()), (kind, inst.name)
+
+
 @pytest.mark.parametrize("algo", ["aspot", "sinkhorn"])
 def test_batched_groups_split_rows(algo):
     """member_elems = 4096 splits every instance above 4096 entries over up to
